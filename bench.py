@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark of the LCS library on one MI355X.
+
+Workload (default): the batched related-pair workload -- 4096 DNA pairs,
+|X| log-uniform in [256, 65536], Y = X mutated at a rate drawn from
+U[5%, 30%] -- with lengths and canonical tracebacks, replayed as a HIP graph.
+One step = one full pass (symbol remap, match masks, bit-parallel fill,
+checkpoints, traceback) over the resident batch.
+
+Prints ONE JSON line.  `value` is whole-job GCUPS (sum of m*n over the batch
+per second); `roofline` refers to the fill kernel, bound by integer VALU
+issue; `cpu_baseline` is the CPU oracle timed on this host on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# gfx950 integer-VALU roofline for the column recurrence: 256 CUs x 64 lanes
+# x 2.4 GHz lane-instructions per second, 6 lane-instructions per 64 cells.
+CUS, LANES, CLOCK_HZ, OPS_PER_64 = 256, 64, 2.4e9, 6
+PEAK_TCUPS = CUS * LANES * CLOCK_HZ * 64 / OPS_PER_64 / 1e12
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(name: str):
+    from paper_1306_4627_amd import inputs
+    if name == "batch_related":
+        ps = inputs.batch_related()
+        return ps, "dna", True, {"workload": "batch_related", "pairs": 4096,
+                                 "len_x": "log-uniform[256,65536]", "alphabet": "DNA",
+                                 "mutation": "U[0.05,0.30] sub/ins/del", "traceback": True,
+                                 "launch": "hipGraph, persistent"}
+    if name == "batch_short":
+        ps = inputs.batch_short()
+        return ps, "protein", False, {"workload": "batch_short", "pairs": 65536,
+                                      "len": "U{64..1024}", "alphabet": "protein(20)",
+                                      "traceback": False, "launch": "hipGraph, persistent"}
+    if name == "pair_dna_4096":
+        p = inputs.pair_dna_4096()
+        return [p], "dna", True, {"workload": "pair_dna_4096", "m": 4096, "n": 4096,
+                                  "alphabet": "DNA", "traceback": True}
+    if name == "pair_long_related":
+        p = inputs.pair_long_related()
+        return [p], "dna", True, {"workload": "pair_long_related", "m": int(p.x.size),
+                                  "n": int(p.y.size), "alphabet": "DNA", "traceback": True}
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(pairs, traceback: bool, budget_cells: float, threads: int):
+    """Time the oracle on a random sample of the workload's pairs."""
+    import oracle
+    g = np.random.default_rng(7)
+    order = g.permutation(len(pairs))
+    sample, cells = [], 0
+    for k in order:
+        p = pairs[k]
+        if cells + p.cells > budget_cells and sample:
+            continue
+        sample.append(p)
+        cells += p.cells
+        if cells >= budget_cells:
+            break
+
+    def one(p):
+        if traceback:
+            if (p.x.size + 1) * (p.y.size + 1) <= 2e8:
+                oracle.lcs_traceback(p.x, p.y)
+            else:
+                oracle.lcs_traceback_ckpt(p.x, p.y, 512)
+        else:
+            oracle.lcs_length(p.x, p.y)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(one, sample))
+    dt = time.perf_counter() - t0
+    return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{len(sample)} random pairs of the workload, {cells:.3e} cells, "
+                      f"{'length+traceback' if traceback else 'length'}, {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="batch_related")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain per-pair leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-cells", type=float, default=6e9)
+    ap.add_argument("--wpl", type=int, default=0)
+    ap.add_argument("--ckpt", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the workload is the one-GPU "
+              "share); --gpus must be 1", file=sys.stderr)
+        return 2
+
+    from paper_1306_4627_amd import lcs
+
+    ps, alpha, tb, config = make_workload(args.workload)
+    pairs = [(p.x, p.y) for p in ps]
+    cells = float(sum(p.cells for p in ps))
+    ctx = lcs.Context(0)
+    log(f"workload {args.workload}: {len(pairs)} pairs, {cells:.3e} cells")
+    batch = lcs.Batch(ctx, pairs, alpha, traceback=tb, graph=True,
+                      words_per_lane=args.wpl, ckpt_interval=args.ckpt)
+    info = batch.info()
+    log(f"plan: {info}")
+    for _ in range(args.warmup):
+        batch.time()
+    fill_ms, total_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        t, f = batch.time()          # graph launch + sync, HIP events inside
+        total_ms.append(t)
+        fill_ms.append(f)
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    value = cells * args.steps / wall / 1e9
+    fill_avg = float(np.mean(fill_ms))
+    achieved = cells / (fill_avg * 1e-3) / 1e12
+    log(f"step {ms_per_step:.3f} ms (events {np.mean(total_ms):.3f} ms), fill {fill_avg:.3f} ms")
+    # correctness spot check against the lengths of the first run
+    lens = batch.lengths()
+
+    out = {
+        "metric": "LCS GCUPS batched vs plain per-pair on 1 MI355X; p50/p99 request latency",
+        "value": round(value, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": config,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_TCUPS, 1),
+                     "unit": "TCUPS", "frac": round(achieved / PEAK_TCUPS, 4), "traffic": None,
+                     "kernel": "k_fill", "fill_ms": round(fill_avg, 4)},
+        "plan": {k: info[k] for k in ("groups", "lanes", "lane_steps", "words_per_lane",
+                                      "ckpt_interval", "classes", "device_bytes")},
+    }
+    if not args.no_plain and len(pairs) > 1:
+        log("plain per-pair leg")
+        with lcs.Batch(ctx, pairs, alpha, traceback=tb, plain=True) as pb:
+            pb.time()
+            t_plain, f_plain = pb.time()
+            plain_l = pb.lengths()
+        if not np.array_equal(plain_l, lens):
+            log("plain and batched lengths differ!")
+            out["plain_mismatch"] = True
+        out["plain_per_pair"] = {"value": round(cells / (t_plain * 1e-3) / 1e9, 2), "unit": "GCUPS",
+                                 "ms": round(t_plain, 3)}
+        out["batched_over_plain"] = round(value / out["plain_per_pair"]["value"], 2)
+    if not args.no_cpu:
+        threads = min(len(os.sched_getaffinity(0)), 16)
+        log(f"cpu oracle leg ({threads} threads)")
+        cb = cpu_baseline(ps, tb, args.cpu_cells, threads)
+        out["cpu_baseline"] = cb
+        out["gpu_over_cpu"] = round(value / cb["value"], 1)
+    batch.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,217 @@
+/*
+ * lcs.h -- C ABI of liblcs_hip.so: exact longest-common-subsequence (LCS)
+ * length and canonical LCS string on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the dynamic program of Dash & Nayak, "Parallel Algorithm
+ * for Longest Common Subsequence in a String" (arXiv:1306.4627):
+ *
+ *   section I.C (procedure LCS-length): with X = x_1..x_m indexing rows and
+ *   Y = y_1..y_n indexing columns, c[i][0] = c[0][j] = 0 and
+ *     c[i][j] = c[i-1][j-1] + 1                 if x_i == y_j   (DIAG)
+ *             = c[i-1][j]   if c[i-1][j] >= c[i][j-1]           (UP)
+ *             = c[i][j-1]   otherwise                           (LEFT)
+ *   and the LCS length is c[m][n];
+ *
+ *   section I.D (procedure Print-LCS): start at (m, n); DIAG emits x_i and
+ *   moves to (i-1, j-1), UP moves to (i-1, j), LEFT moves to (i, j-1); the
+ *   emitted symbols, reversed, are the canonical LCS (ties go UP).
+ *
+ * The library computes exactly these values (bit-identical lengths and
+ * strings); it never builds the tables.  Arguments are not symmetric for the
+ * string: lcs_traceback(x, y) and lcs_traceback(y, x) may differ, the length
+ * never does.  The returned string consists of bytes of X in forward order.
+ *
+ * Conventions for every entry point:
+ *  - all pointers are HOST pointers unless the name says otherwise; the
+ *    caller owns every buffer passed in and every buffer written to; nothing
+ *    is returned that the caller must free except the opaque handles, which
+ *    are released with their destroy call;
+ *  - a sequence pointer may be NULL only when its length is 0;
+ *  - on any negative status, no output buffer has been written;
+ *  - m == 0 or n == 0 is valid (length 0, empty string);
+ *  - calls on one context are not thread-safe; use one context per thread.
+ */
+#ifndef LCS_H_
+#define LCS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LCS_OK = 0,
+    LCS_ERR_ARG = -1,         /* NULL pointer with non-zero length, bad flag or size */
+    LCS_ERR_SYMBOL = -2,      /* a byte of X or Y is not in the alphabet */
+    LCS_ERR_NOMEM = -3,       /* device memory budget or host memory exhausted */
+    LCS_ERR_DEVICE = -4,      /* no usable gfx950 device, or a HIP runtime error */
+    LCS_ERR_BUFFER = -5,      /* caller's output buffer is smaller than the worst case */
+    LCS_ERR_TOO_LONG = -6,    /* a sequence is longer than LCS_MAX_LEN */
+    LCS_ERR_UNSUPPORTED = -7  /* tuning request the library cannot honour */
+} lcs_status;
+
+/* Longest accepted sequence (|X| and |Y|), 2^31 - 1 symbols. */
+#define LCS_MAX_LEN 2147483647ull
+
+/* The alphabet of the input bytes (paper section I: DNA strands are strings
+ * over {A, C, G, T}).  `size` is 1..256 and `symbols` lists `size` distinct
+ * bytes; symbols == NULL with size == 256 means "every byte value".  Symbols
+ * are compared as raw bytes (case-sensitive). */
+typedef struct {
+    uint16_t size;
+    const uint8_t *symbols;
+} lcs_alphabet;
+
+/* One input pair: X (rows, length m) and Y (columns, length n). */
+typedef struct {
+    const uint8_t *x;
+    uint64_t m;
+    const uint8_t *y;
+    uint64_t n;
+} lcs_pair;
+
+/* Opaque context: one device, one HIP stream, a device-memory budget. */
+typedef struct lcs_ctx lcs_ctx;
+
+/* Opaque resident batch: inputs uploaded once, run many times. */
+typedef struct lcs_batch lcs_batch;
+
+/* Batch flags. */
+#define LCS_WANT_TRACEBACK 1u   /* also recover the canonical LCS of each pair */
+#define LCS_USE_GRAPH      2u   /* replay the launch sequence as a HIP graph */
+
+/* Tuning knobs; a zero field means "choose automatically".
+ *  words_per_lane  : 64-bit words of the bit-vector column held per lane
+ *                    (1, 2, 4 or 8);
+ *  ckpt_interval   : columns between stored bit-vector checkpoints for the
+ *                    traceback (multiple of 64);
+ *  persistent_waves: cap on resident work-groups of the persistent kernels;
+ *  plain           : 1 = no packing: one pair per work-group and one launch
+ *                    per pair (the plain per-pair path, for comparison). */
+typedef struct {
+    int32_t words_per_lane;
+    int32_t ckpt_interval;
+    int32_t persistent_waves;
+    int32_t plain;
+} lcs_tuning;
+
+/* What a batch was planned into (filled by lcs_batch_info). */
+typedef struct {
+    uint64_t pairs;          /* pairs in the batch */
+    uint64_t cells;          /* sum of m*n over the pairs */
+    uint64_t groups;         /* packed work items (all classes) */
+    uint64_t lanes;          /* lanes of all work items, busy or idle */
+    uint64_t lane_steps;     /* sum over work items of lanes * steps */
+    uint64_t device_bytes;   /* device memory held by the batch */
+    int32_t words_per_lane;  /* as chosen */
+    int32_t ckpt_interval;   /* as chosen (0 without traceback) */
+    int32_t classes;         /* kernel launches per run (fill) */
+    int32_t flags;           /* LCS_WANT_TRACEBACK / LCS_USE_GRAPH as planned */
+} lcs_batch_stats;
+
+/* Text for a status code; never NULL; static storage. */
+const char *lcs_status_str(int status);
+
+/* Library version string; static storage. */
+const char *lcs_version(void);
+
+/* Create a context on HIP device `device`.  mem_budget_bytes caps the device
+ * memory the context's batches may hold (0 = 90% of the device's free memory
+ * at creation).  Returns LCS_ERR_DEVICE when the device is absent or is not a
+ * gfx950 part.  *out is written only on success. */
+lcs_status lcs_create(lcs_ctx **out, int device, size_t mem_budget_bytes);
+
+/* Release a context and everything it holds (NULL is ignored).  Batches
+ * created on it must have been destroyed first. */
+void lcs_destroy(lcs_ctx *ctx);
+
+/* Make subsequent work of `ctx` run on `hip_stream` (a hipStream_t of the
+ * context's device, e.g. torch.cuda.current_stream().cuda_stream on ROCm);
+ * NULL selects the context's own stream.  The caller keeps the stream alive. */
+lcs_status lcs_set_stream(lcs_ctx *ctx, void *hip_stream);
+
+/* Wait for all work queued on the context's stream. */
+lcs_status lcs_synchronize(lcs_ctx *ctx);
+
+/* LCS length of one pair (section I.C: c[m][n]).  Blocks until done. */
+lcs_status lcs_length(lcs_ctx *ctx, const uint8_t *x, uint64_t m,
+                      const uint8_t *y, uint64_t n, const lcs_alphabet *alphabet,
+                      uint64_t *out_len);
+
+/* Canonical LCS of one pair (sections I.C and I.D).  `out` receives
+ * *out_len bytes of X in forward order; out_cap must be >= min(m, n)
+ * (LCS_ERR_BUFFER otherwise).  Blocks until done. */
+lcs_status lcs_traceback(lcs_ctx *ctx, const uint8_t *x, uint64_t m,
+                         const uint8_t *y, uint64_t n, const lcs_alphabet *alphabet,
+                         uint8_t *out, uint64_t out_cap, uint64_t *out_len);
+
+/* LCS lengths of `count` pairs, one packed persistent launch per class.
+ * out_lens[k] is the length of pairs[k].  Blocks until done. */
+lcs_status lcs_length_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                            const lcs_alphabet *alphabet, uint64_t *out_lens);
+
+/* Canonical LCS of `count` pairs.  The strings are written back to back into
+ * out_arena: pair k occupies out_lens[k] bytes at out_offsets[k].  arena_cap
+ * must be >= sum over pairs of min(m, n) (LCS_ERR_BUFFER otherwise).  Blocks
+ * until done. */
+lcs_status lcs_traceback_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                               const lcs_alphabet *alphabet, uint8_t *out_arena,
+                               uint64_t arena_cap, uint64_t *out_offsets,
+                               uint64_t *out_lens);
+
+/* Plan and upload a batch without running it.  The input bytes are copied to
+ * device memory; the caller's host buffers may be released afterwards.
+ * flags: LCS_WANT_TRACEBACK | LCS_USE_GRAPH.  tuning may be NULL (automatic).
+ * Fails with LCS_ERR_NOMEM when the batch would exceed the context budget. */
+lcs_status lcs_batch_create(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                            const lcs_alphabet *alphabet, uint32_t flags,
+                            const lcs_tuning *tuning, lcs_batch **out);
+
+/* Enqueue one full pass (symbol remap, match masks, fill, length and, if
+ * planned, traceback) on the context's stream.  Asynchronous; inputs stay
+ * resident, so repeated runs recompute from the same device data. */
+lcs_status lcs_batch_run(lcs_batch *batch);
+
+/* Wait for the batch's last run and copy its lengths (input order). */
+lcs_status lcs_batch_lengths(lcs_batch *batch, uint64_t *out_lens);
+
+/* Wait for the batch's last run and copy its strings, laid out as in
+ * lcs_traceback_batch.  LCS_ERR_ARG if the batch was planned without
+ * LCS_WANT_TRACEBACK. */
+lcs_status lcs_batch_tracebacks(lcs_batch *batch, uint8_t *out_arena, uint64_t arena_cap,
+                                uint64_t *out_offsets, uint64_t *out_lens);
+
+/* Describe how the batch was planned. */
+lcs_status lcs_batch_info(const lcs_batch *batch, lcs_batch_stats *out);
+
+/* Run the batch once (as lcs_batch_run does, graph or not), wait for it and
+ * report its HIP-event timings (inputs already resident).  *total_ms
+ * receives the duration of the whole pass, *fill_ms that of the fill kernels
+ * alone (-1 if they could not be timed separately); either may be NULL. */
+lcs_status lcs_batch_time(lcs_batch *batch, float *total_ms, float *fill_ms);
+
+/* Release a batch (NULL is ignored). */
+void lcs_batch_destroy(lcs_batch *batch);
+
+/* Host-only planning check (no device needed).  Packs `count` pairs of the
+ * given lengths for `words_per_lane` and reports the same figures
+ * lcs_batch_info would (device_bytes excluded).  Used to test the packer. */
+lcs_status lcs_plan_describe(const uint64_t *m, const uint64_t *n, uint64_t count,
+                             uint16_t alphabet_size, uint32_t flags,
+                             const lcs_tuning *tuning, lcs_batch_stats *out);
+
+/* Host-only: validate the packer's lane assignment for the given lengths --
+ * every pair covered by exactly ceil(ceil(m/64)/words_per_lane) consecutive
+ * lanes of one work item, no lane shared, every carry hand-over in bounds.
+ * Returns LCS_OK when all checks hold, LCS_ERR_ARG otherwise. */
+lcs_status lcs_plan_selfcheck(const uint64_t *m, const uint64_t *n, uint64_t count,
+                              uint16_t alphabet_size, uint32_t flags,
+                              const lcs_tuning *tuning);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LCS_H_ */

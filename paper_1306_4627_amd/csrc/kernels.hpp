@@ -1,0 +1,100 @@
+// kernels.hpp -- argument blocks and launchers of the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace lcs {
+
+// Symbol remap and Y-stream construction (all device pointers).
+struct PrepArgs {
+    const uint8_t *lut;        // 256 entries: byte -> code (validated on the host)
+    const uint8_t *xbytes;     // X arena (raw bytes)
+    uint8_t *xcodes;           // X arena (codes), same offsets
+    uint64_t xarena;           // bytes in the X arena
+    const uint8_t *ybytes;     // Y arena (raw bytes)
+    const uint64_t *seg_yoff;  // per stream region: offset of its Y in the Y arena
+    const uint32_t *seg_n;     // columns of its pair (0 for an all-sentinel region)
+    const uint64_t *seg_begin; // first element of the region
+    const uint32_t *seg_pre;   // sentinel elements before column 0
+    const uint64_t *seg_len;   // region length in elements
+    const uint8_t *seg_shift;  // log2 of the stream scale (words_per_lane * 512)
+    uint32_t nseg;
+    uint16_t *ystream;         // element = code << seg_shift
+    uint32_t sentinel;         // code whose match mask is zero (= alphabet size)
+    uint64_t *out_len;         // zeroed here (per pair)
+    uint32_t npairs;
+    uint32_t *zero_words;      // counters/flags zeroed here
+    uint64_t nzero;
+};
+
+// Fill: one class (fixed words per lane), persistent waves.
+struct FillArgs {
+    const uint8_t *xcodes;
+    const uint64_t *pair_xoff;
+    const uint32_t *pair_m;
+    const uint16_t *ystream;   // per class: code * (words_per_lane * 512)
+    const uint32_t *it_T;
+    const int32_t *it_prev;
+    const uint8_t *it_feeds;
+    const uint64_t *it_ck;
+    const uint64_t *it_cb;
+    const uint64_t *it_xf;
+    const int32_t *ln_pair;
+    const uint32_t *ln_word0;
+    const uint32_t *ln_skew;
+    const uint64_t *ln_ys;
+    uint64_t *out_len;
+    uint64_t *ckpt;
+    uint32_t *cbits;
+    uint64_t *xfer;
+    uint32_t *progress;        // per item: chunks completed (feeders only)
+    uint32_t *queue;           // work counter (zeroed before the launch)
+    uint32_t *error;           // set to 1 when a bounded wait runs out
+    uint32_t item_begin;
+    uint32_t item_end;
+    uint32_t spin_limit;       // polls before a wait gives up
+    int32_t sigma;             // code sigma is the zero-mask sentinel
+    int32_t ckpt_every;        // steps between checkpoints (traceback only)
+};
+
+// Traceback: one wave per pair, persistent.
+struct TbArgs {
+    const uint8_t *xcodes;
+    const uint8_t *xbytes;
+    const uint64_t *pair_xoff;
+    const uint32_t *pair_m;
+    const uint32_t *pair_n;
+    const uint64_t *pair_out;  // offset of each pair's string in `out`
+    const uint64_t *out_len;
+    const uint16_t *ystream;   // per class: code * (words_per_lane * 512)
+    const uint64_t *it_ck;
+    const uint64_t *it_cb;
+    const uint32_t *ln_skew;
+    const uint64_t *ln_ys;
+    const uint64_t *ckpt;
+    const uint32_t *cbits;
+    const uint32_t *tb_pair;
+    const uint32_t *tb_item;
+    const uint32_t *tb_lane0;
+    uint32_t ntb;
+    uint8_t *out;
+    uint32_t *queue;
+    int32_t sigma;
+    int32_t ckpt_every;
+};
+
+constexpr int kFillBlock = 256;   // four independent waves per work-group
+constexpr int kTbBlock = 256;
+
+size_t fill_lds_bytes(int wpl, int sigma);
+size_t tb_lds_bytes(int wpl, int sigma, int ckpt_every);
+
+const void *fill_symbol(int wpl, bool tb);
+const void *tb_symbol(int wpl);
+
+hipError_t launch_prep(const PrepArgs &a, uint64_t xbytes_n, hipStream_t s);
+hipError_t launch_fill(int wpl, bool traceback, const FillArgs &a, uint32_t grid, hipStream_t s);
+hipError_t launch_tb(int wpl, const TbArgs &a, uint32_t grid, hipStream_t s);
+
+}  // namespace lcs

@@ -1,0 +1,924 @@
+// lcs_api.hip -- C ABI of the LCS library (see include/lcs.h): contexts,
+// validation, symbol remap tables, device memory, launch sequences, HIP
+// graphs and result copies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lcs.h"
+#include "plan.hpp"
+
+using namespace lcs;
+
+#define LCS_VERSION_STRING "lcs-mi355x 0.1 (gfx950)"
+
+struct lcs_ctx {
+    int device = 0;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    size_t budget = 0;
+    size_t in_use = 0;
+    int num_cus = 0;
+    std::string arch;
+};
+
+namespace {
+
+struct ClassDev {
+    int wpl = 1;
+    uint32_t nitems = 0, ntb = 0;
+    uint32_t *it_T = nullptr;
+    int32_t *it_prev = nullptr;
+    uint8_t *it_feeds = nullptr;
+    uint64_t *it_ck = nullptr, *it_cb = nullptr, *it_xf = nullptr;
+    int32_t *ln_pair = nullptr;
+    uint32_t *ln_word0 = nullptr, *ln_skew = nullptr;
+    uint64_t *ln_ys = nullptr;
+    uint32_t *tb_pair = nullptr, *tb_item = nullptr, *tb_lane0 = nullptr;
+    uint64_t *ckpt = nullptr;
+    uint32_t *cbits = nullptr;
+    uint64_t *xfer = nullptr;
+    uint32_t *progress = nullptr;
+    uint32_t *q_fill = nullptr, *q_tb = nullptr;
+    uint32_t fill_grid = 1, tb_grid = 1;
+    // plain mode: one launch per pair
+    std::vector<uint32_t> pl_pair;     // pair of each launch
+    std::vector<uint32_t> pl_begin, pl_end, pl_tb;  // item range, index in tb list
+};
+
+// Bump allocator over one device allocation.
+struct Carver {
+    char *base = nullptr;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace
+
+struct lcs_batch {
+    lcs_ctx *ctx = nullptr;
+    uint32_t flags = 0;
+    int sigma = 0;
+    int ckpt = 0;
+    bool plain = false;
+    uint32_t spin_limit = 1u << 26;
+    Plan plan;
+    uint64_t npairs = 0;
+    std::vector<uint64_t> m, n;
+    std::vector<uint64_t> out_off_host;   // worst-case slot of each pair
+    uint64_t out_bytes = 0;
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    uint8_t *lut = nullptr, *xbytes = nullptr, *xcodes = nullptr, *ybytes = nullptr;
+    uint64_t xarena = 0, yarena = 0;
+    uint64_t *pair_xoff = nullptr, *pair_yoff = nullptr, *pair_out = nullptr, *out_len = nullptr;
+    uint32_t *pair_m = nullptr, *pair_n = nullptr;
+    uint64_t *seg_yoff = nullptr, *seg_begin = nullptr, *seg_len = nullptr;
+    uint32_t *seg_n = nullptr, *seg_pre = nullptr;
+    uint8_t *seg_shift = nullptr;
+    uint16_t *ystream = nullptr;
+    uint8_t *out = nullptr;
+    uint32_t *zero = nullptr;
+    uint64_t nzero = 0;
+    uint32_t *error = nullptr;
+    std::vector<ClassDev> cls;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool ran = false;
+    bool graph_events = false;   // the graph records the four events itself
+    bool timed_fill = false;     // the last pass recorded the fill events
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+// --------------------------------------------------------------------------
+// small helpers
+// --------------------------------------------------------------------------
+
+static lcs_status dev_err(hipError_t e) {
+    return e == hipSuccess ? LCS_OK : (e == hipErrorOutOfMemory ? LCS_ERR_NOMEM : LCS_ERR_DEVICE);
+}
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return dev_err(e_);      \
+    } while (0)
+
+// Build the byte -> code table: codes 0..size-1 in the order the alphabet
+// lists its symbols; valid[b] says whether byte b belongs to the alphabet.
+static lcs_status make_lut(const lcs_alphabet *a, uint8_t lut[256], bool valid[256], int *sigma) {
+    if (!a || a->size < 1 || a->size > 256) return LCS_ERR_ARG;
+    std::memset(lut, 0, 256);
+    for (int k = 0; k < 256; ++k) valid[k] = false;
+    if (!a->symbols) {
+        if (a->size != 256) return LCS_ERR_ARG;
+        for (int k = 0; k < 256; ++k) { lut[k] = (uint8_t)k; valid[k] = true; }
+    } else {
+        for (int k = 0; k < a->size; ++k) {
+            uint8_t s = a->symbols[k];
+            if (valid[s]) return LCS_ERR_ARG;   // repeated symbol
+            valid[s] = true;
+            lut[s] = (uint8_t)k;
+        }
+    }
+    *sigma = a->size;
+    return LCS_OK;
+}
+
+static bool all_in(const uint8_t *s, uint64_t len, const bool valid[256]) {
+    for (uint64_t k = 0; k < len; ++k)
+        if (!valid[s[k]]) return false;
+    return true;
+}
+
+static lcs_status check_pairs(const lcs_pair *pairs, uint64_t count) {
+    if (count && !pairs) return LCS_ERR_ARG;
+    for (uint64_t k = 0; k < count; ++k) {
+        const lcs_pair &p = pairs[k];
+        if ((p.m && !p.x) || (p.n && !p.y)) return LCS_ERR_ARG;
+        if (p.m > LCS_MAX_LEN || p.n > LCS_MAX_LEN) return LCS_ERR_TOO_LONG;
+    }
+    return LCS_OK;
+}
+
+static lcs_status check_tuning(const lcs_tuning *t) {
+    if (!t) return LCS_OK;
+    if (t->words_per_lane != 0 && t->words_per_lane != 1 && t->words_per_lane != 2 &&
+        t->words_per_lane != 4 && t->words_per_lane != 8)
+        return LCS_ERR_ARG;
+    if (t->ckpt_interval < 0 || (t->ckpt_interval % 64) != 0) return LCS_ERR_ARG;
+    if (t->persistent_waves < 0 || t->plain < 0 || t->plain > 1) return LCS_ERR_ARG;
+    return LCS_OK;
+}
+
+static void fill_plan_config(PlanConfig &cfg, int sigma, uint32_t flags, const lcs_tuning *t) {
+    cfg.wpl = t ? t->words_per_lane : 0;
+    cfg.traceback = (flags & LCS_WANT_TRACEBACK) != 0;
+    cfg.ckpt = (t && t->ckpt_interval) ? t->ckpt_interval : 128;
+    cfg.sigma = sigma;
+    cfg.plain = t && t->plain;
+}
+
+static void stats_from_plan(const Plan &p, uint64_t npairs, lcs_batch_stats *out) {
+    std::memset(out, 0, sizeof *out);
+    out->pairs = npairs;
+    out->cells = p.cells;
+    out->groups = p.items;
+    out->lanes = p.lanes;
+    out->lane_steps = p.lane_steps;
+    int w = 0;
+    for (const ClassPlan &c : p.classes) w = std::max(w, c.wpl);
+    out->words_per_lane = w;
+    out->ckpt_interval = p.cfg.traceback ? p.cfg.ckpt : 0;
+    out->classes = (int32_t)p.classes.size();
+    out->flags = p.cfg.traceback ? (int32_t)LCS_WANT_TRACEBACK : 0;
+}
+
+// --------------------------------------------------------------------------
+// status, version
+// --------------------------------------------------------------------------
+
+extern "C" const char *lcs_status_str(int s) {
+    switch (s) {
+        case LCS_OK: return "ok";
+        case LCS_ERR_ARG: return "invalid argument";
+        case LCS_ERR_SYMBOL: return "symbol not in alphabet";
+        case LCS_ERR_NOMEM: return "out of memory (device budget or host)";
+        case LCS_ERR_DEVICE: return "device error (no gfx950 device or HIP failure)";
+        case LCS_ERR_BUFFER: return "output buffer too small";
+        case LCS_ERR_TOO_LONG: return "sequence too long";
+        case LCS_ERR_UNSUPPORTED: return "unsupported tuning or alphabet";
+        default: return "unknown status";
+    }
+}
+
+extern "C" const char *lcs_version(void) { return LCS_VERSION_STRING; }
+
+// --------------------------------------------------------------------------
+// context
+// --------------------------------------------------------------------------
+
+extern "C" lcs_status lcs_create(lcs_ctx **out, int device, size_t mem_budget_bytes) {
+    if (!out) return LCS_ERR_ARG;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return LCS_ERR_DEVICE;
+    if (device < 0 || device >= count) return LCS_ERR_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return LCS_ERR_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LCS_ERR_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return LCS_ERR_DEVICE;
+    std::unique_ptr<lcs_ctx> c(new (std::nothrow) lcs_ctx());
+    if (!c) return LCS_ERR_NOMEM;
+    c->device = device;
+    c->num_cus = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
+    if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess)
+        return LCS_ERR_DEVICE;
+    c->stream = c->own_stream;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipStreamDestroy(c->own_stream);
+        return LCS_ERR_DEVICE;
+    }
+    c->budget = mem_budget_bytes ? mem_budget_bytes : (size_t)(fr * 0.9);
+    *out = c.release();
+    return LCS_OK;
+}
+
+extern "C" void lcs_destroy(lcs_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->own_stream) {
+        (void)hipStreamSynchronize(ctx->own_stream);
+        (void)hipStreamDestroy(ctx->own_stream);
+    }
+    delete ctx;
+}
+
+extern "C" lcs_status lcs_set_stream(lcs_ctx *ctx, void *hip_stream) {
+    if (!ctx) return LCS_ERR_ARG;
+    ctx->stream = hip_stream ? (hipStream_t)hip_stream : ctx->own_stream;
+    return LCS_OK;
+}
+
+extern "C" lcs_status lcs_synchronize(lcs_ctx *ctx) {
+    if (!ctx) return LCS_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
+    return dev_err(hipStreamSynchronize(ctx->stream));
+}
+
+// --------------------------------------------------------------------------
+// batches
+// --------------------------------------------------------------------------
+
+static void free_batch(lcs_batch *b) {
+    if (!b) return;
+    if (b->ctx) (void)hipSetDevice(b->ctx->device);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (hipEvent_t &e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (b->dev) {
+        (void)hipFree(b->dev);
+        if (b->ctx) b->ctx->in_use -= b->dev_bytes;
+    }
+    delete b;
+}
+
+// Lay out (or, with base == nullptr, just size) the device memory of a batch.
+static size_t carve(lcs_batch *b, char *base) {
+    Carver cv;
+    cv.base = base;
+    const Plan &p = b->plan;
+    const uint64_t np = b->npairs;
+    b->lut = cv.take<uint8_t>(256);
+    b->xbytes = cv.take<uint8_t>(b->xarena + 64);
+    b->xcodes = cv.take<uint8_t>(b->xarena + 64);
+    b->ybytes = cv.take<uint8_t>(b->yarena + 64);
+    b->pair_xoff = cv.take<uint64_t>(np + 1);
+    b->pair_yoff = cv.take<uint64_t>(np + 1);
+    b->pair_out = cv.take<uint64_t>(np + 1);
+    b->out_len = cv.take<uint64_t>(np + 1);
+    b->pair_m = cv.take<uint32_t>(np + 1);
+    b->pair_n = cv.take<uint32_t>(np + 1);
+    const size_t ns = p.segs.size();
+    b->seg_yoff = cv.take<uint64_t>(ns + 1);
+    b->seg_begin = cv.take<uint64_t>(ns + 1);
+    b->seg_len = cv.take<uint64_t>(ns + 1);
+    b->seg_n = cv.take<uint32_t>(ns + 1);
+    b->seg_pre = cv.take<uint32_t>(ns + 1);
+    b->seg_shift = cv.take<uint8_t>(ns + 1);
+    b->ystream = cv.take<uint16_t>(p.ys_elems + 64);
+    b->out = cv.take<uint8_t>(b->out_bytes + 64);
+    // zeroed words: per class fill/tb counters, per-pair plain counters,
+    // per item progress flags, error flag
+    b->cls.resize(p.classes.size());
+    uint64_t nz = 1;   // error word first
+    for (size_t ci = 0; ci < p.classes.size(); ++ci) {
+        const ClassPlan &C = p.classes[ci];
+        nz += 2 + C.it_T.size();
+        if (b->plain) nz += 2 * C.tb_pair.size();
+    }
+    b->zero = cv.take<uint32_t>(nz);
+    b->nzero = nz;
+    b->error = b->zero;
+    uint64_t zc = 1;
+    for (size_t ci = 0; ci < p.classes.size(); ++ci) {
+        const ClassPlan &C = p.classes[ci];
+        ClassDev &D = b->cls[ci];
+        D.wpl = C.wpl;
+        D.nitems = (uint32_t)C.it_T.size();
+        D.ntb = (uint32_t)C.tb_pair.size();
+        D.it_T = cv.take<uint32_t>(D.nitems);
+        D.it_prev = cv.take<int32_t>(D.nitems);
+        D.it_feeds = cv.take<uint8_t>(D.nitems);
+        D.it_ck = cv.take<uint64_t>(D.nitems);
+        D.it_cb = cv.take<uint64_t>(D.nitems);
+        D.it_xf = cv.take<uint64_t>(D.nitems);
+        D.ln_pair = cv.take<int32_t>(C.ln_pair.size());
+        D.ln_word0 = cv.take<uint32_t>(C.ln_pair.size());
+        D.ln_skew = cv.take<uint32_t>(C.ln_pair.size());
+        D.ln_ys = cv.take<uint64_t>(C.ln_pair.size());
+        D.tb_pair = cv.take<uint32_t>(D.ntb + 1);
+        D.tb_item = cv.take<uint32_t>(D.ntb + 1);
+        D.tb_lane0 = cv.take<uint32_t>(D.ntb + 1);
+        D.ckpt = cv.take<uint64_t>(C.ck_words + 1);
+        D.cbits = cv.take<uint32_t>(C.cb_words + 1);
+        D.xfer = cv.take<uint64_t>(C.xf_words + 1);
+        D.q_fill = b->zero ? b->zero + zc : nullptr;
+        D.q_tb = b->zero ? b->zero + zc + 1 : nullptr;
+        zc += 2;
+        D.progress = b->zero ? b->zero + zc : nullptr;
+        zc += D.nitems;
+        if (b->plain) zc += 2 * D.ntb;
+    }
+    return cv.off + 256;
+}
+
+// Persistent grid: as many work-groups as can be resident, capped by work.
+static uint32_t resident_grid(lcs_ctx *ctx, const void *fn, size_t lds, uint64_t work_groups,
+                              int cap) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kFillBlock, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    uint64_t g = (uint64_t)per_cu * (uint64_t)ctx->num_cus;
+    if (cap > 0) g = std::min<uint64_t>(g, (uint64_t)cap);
+    g = std::min<uint64_t>(g, std::max<uint64_t>(work_groups, 1));
+    return (uint32_t)std::max<uint64_t>(g, 1);
+}
+
+static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                              const lcs_alphabet *alphabet, uint32_t flags,
+                              const lcs_tuning *tuning, lcs_batch **out) {
+    if (!ctx || !out) return LCS_ERR_ARG;
+    if (flags & ~(uint32_t)(LCS_WANT_TRACEBACK | LCS_USE_GRAPH)) return LCS_ERR_ARG;
+    lcs_status st = check_pairs(pairs, count);
+    if (st) return st;
+    st = check_tuning(tuning);
+    if (st) return st;
+    uint8_t lut[256];
+    bool valid[256];
+    int sigma = 0;
+    st = make_lut(alphabet, lut, valid, &sigma);
+    if (st) return st;
+    for (uint64_t k = 0; k < count; ++k) {
+        if (!all_in(pairs[k].x, pairs[k].m, valid)) return LCS_ERR_SYMBOL;
+        if (!all_in(pairs[k].y, pairs[k].n, valid)) return LCS_ERR_SYMBOL;
+    }
+    std::unique_ptr<lcs_batch> b(new (std::nothrow) lcs_batch());
+    if (!b) return LCS_ERR_NOMEM;
+    b->ctx = ctx;
+    b->flags = flags;
+    b->sigma = sigma;
+    b->plain = tuning && tuning->plain;
+    b->npairs = count;
+    std::vector<PairShape> shapes(count);
+    b->m.resize(count);
+    b->n.resize(count);
+    b->out_off_host.resize(count + 1);
+    uint64_t xa = 0, ya = 0, oo = 0;
+    std::vector<uint64_t> xoff(count + 1), yoff(count + 1);
+    for (uint64_t k = 0; k < count; ++k) {
+        shapes[k].m = b->m[k] = pairs[k].m;
+        shapes[k].n = b->n[k] = pairs[k].n;
+        xoff[k] = xa;
+        yoff[k] = ya;
+        xa += (pairs[k].m + 63) / 64 * 64;   // padded: the fill reads whole dwords
+        ya += pairs[k].n;
+        b->out_off_host[k] = oo;
+        oo += std::min(pairs[k].m, pairs[k].n);
+    }
+    b->out_off_host[count] = oo;
+    b->xarena = xa;
+    b->yarena = ya;
+    b->out_bytes = (flags & LCS_WANT_TRACEBACK) ? oo : 0;
+    PlanConfig cfg;
+    fill_plan_config(cfg, sigma, flags, tuning);
+    if (sigma > 127 || max_wpl(sigma) == 0) return LCS_ERR_UNSUPPORTED;
+    if (cfg.wpl && !wpl_fits(sigma, cfg.wpl)) return LCS_ERR_UNSUPPORTED;
+    std::string why = build_plan(shapes, cfg, b->plan);
+    if (!why.empty()) {
+        if (why.find("longer") != std::string::npos || why.find("too long") != std::string::npos ||
+            why.find("too many") != std::string::npos)
+            return LCS_ERR_TOO_LONG;
+        return LCS_ERR_UNSUPPORTED;
+    }
+    b->ckpt = cfg.ckpt;
+    const size_t need = carve(b.get(), nullptr);
+    if (ctx->in_use + need > ctx->budget) return LCS_ERR_NOMEM;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
+    void *mem = nullptr;
+    hipError_t e = hipMalloc(&mem, need);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? LCS_ERR_NOMEM : LCS_ERR_DEVICE;
+    b->dev = mem;
+    b->dev_bytes = need;
+    ctx->in_use += need;
+    carve(b.get(), (char *)mem);
+    lcs_batch *bp = b.release();
+
+    // ---- host staging of everything the device needs ----
+    auto fail = [&](lcs_status s) {
+        free_batch(bp);
+        return s;
+    };
+    std::vector<uint8_t> hx(xa + 64, 0), hy(ya + 64, 0);
+    for (uint64_t k = 0; k < count; ++k) {
+        if (pairs[k].m) std::memcpy(hx.data() + xoff[k], pairs[k].x, pairs[k].m);
+        if (pairs[k].n) std::memcpy(hy.data() + yoff[k], pairs[k].y, pairs[k].n);
+    }
+    std::vector<uint32_t> hm(count + 1, 0), hn(count + 1, 0);
+    for (uint64_t k = 0; k < count; ++k) {
+        hm[k] = (uint32_t)pairs[k].m;
+        hn[k] = (uint32_t)pairs[k].n;
+    }
+    const Plan &p = bp->plan;
+    const size_t ns = p.segs.size();
+    std::vector<uint64_t> s_yoff(ns + 1, 0), s_begin(ns + 1, 0), s_len(ns + 1, 0);
+    std::vector<uint32_t> s_n(ns + 1, 0), s_pre(ns + 1, 0);
+    std::vector<uint8_t> s_shift(ns + 1, 0);
+    for (size_t s = 0; s < ns; ++s) {
+        const Segment &sg = p.segs[s];
+        s_begin[s] = sg.begin;
+        s_len[s] = sg.len;
+        s_pre[s] = sg.pre;
+        s_shift[s] = sg.shift;
+        if (sg.pair != kNoPair) {
+            s_n[s] = (uint32_t)pairs[sg.pair].n;
+            s_yoff[s] = yoff[sg.pair];
+        }
+    }
+    hipStream_t st0 = ctx->own_stream;
+    auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st0);
+    };
+#define UP(dst, src, bytes)                          \
+    do {                                             \
+        hipError_t e_ = up((dst), (src), (bytes));   \
+        if (e_ != hipSuccess) return fail(dev_err(e_)); \
+    } while (0)
+    UP(bp->lut, lut, 256);
+    UP(bp->xbytes, hx.data(), xa + 64);
+    UP(bp->ybytes, hy.data(), ya + 64);
+    UP(bp->pair_xoff, xoff.data(), count * 8);
+    UP(bp->pair_yoff, yoff.data(), count * 8);
+    UP(bp->pair_out, bp->out_off_host.data(), count * 8);
+    UP(bp->pair_m, hm.data(), count * 4);
+    UP(bp->pair_n, hn.data(), count * 4);
+    UP(bp->seg_yoff, s_yoff.data(), ns * 8);
+    UP(bp->seg_begin, s_begin.data(), ns * 8);
+    UP(bp->seg_len, s_len.data(), ns * 8);
+    UP(bp->seg_n, s_n.data(), ns * 4);
+    UP(bp->seg_pre, s_pre.data(), ns * 4);
+    UP(bp->seg_shift, s_shift.data(), ns);
+    for (size_t ci = 0; ci < p.classes.size(); ++ci) {
+        const ClassPlan &C = p.classes[ci];
+        ClassDev &D = bp->cls[ci];
+        UP(D.it_T, C.it_T.data(), C.it_T.size() * 4);
+        UP(D.it_prev, C.it_prev.data(), C.it_prev.size() * 4);
+        UP(D.it_feeds, C.it_feeds.data(), C.it_feeds.size());
+        UP(D.it_ck, C.it_ck.data(), C.it_ck.size() * 8);
+        UP(D.it_cb, C.it_cb.data(), C.it_cb.size() * 8);
+        UP(D.it_xf, C.it_xf.data(), C.it_xf.size() * 8);
+        UP(D.ln_pair, C.ln_pair.data(), C.ln_pair.size() * 4);
+        UP(D.ln_word0, C.ln_word0.data(), C.ln_word0.size() * 4);
+        UP(D.ln_skew, C.ln_skew.data(), C.ln_skew.size() * 4);
+        UP(D.ln_ys, C.ln_ys.data(), C.ln_ys.size() * 8);
+        UP(D.tb_pair, C.tb_pair.data(), C.tb_pair.size() * 4);
+        UP(D.tb_item, C.tb_item.data(), C.tb_item.size() * 4);
+        UP(D.tb_lane0, C.tb_lane0.data(), C.tb_lane0.size() * 4);
+        const int cap = tuning ? tuning->persistent_waves : 0;
+        D.fill_grid = resident_grid(ctx, fill_symbol(C.wpl, cfg.traceback),
+                                    fill_lds_bytes(C.wpl, sigma), (D.nitems + 3) / 4,
+                                    cap > 0 ? (cap + 3) / 4 : 0);
+        D.tb_grid = resident_grid(ctx, tb_symbol(C.wpl), tb_lds_bytes(C.wpl, sigma, cfg.ckpt),
+                                  (D.ntb + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
+        if (bp->plain) {
+            // one launch per pair: items of a pair are consecutive
+            for (uint32_t t = 0; t < D.ntb; ++t) {
+                const uint32_t pr = C.tb_pair[t];
+                uint32_t first = C.tb_item[t], last = first;
+                while (last + 1 < D.nitems && C.it_prev[last + 1] == (int32_t)last) ++last;
+                D.pl_pair.push_back(pr);
+                D.pl_begin.push_back(first);
+                D.pl_end.push_back(last + 1);
+                D.pl_tb.push_back(t);
+            }
+        }
+    }
+#undef UP
+    if (hipStreamSynchronize(st0) != hipSuccess) return fail(LCS_ERR_DEVICE);
+    for (hipEvent_t &ev : bp->ev)
+        if (hipEventCreate(&ev) != hipSuccess) return fail(LCS_ERR_DEVICE);
+    *out = bp;
+    return LCS_OK;
+}
+
+extern "C" lcs_status lcs_batch_create(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                                       const lcs_alphabet *alphabet, uint32_t flags,
+                                       const lcs_tuning *tuning, lcs_batch **out) {
+    return build_batch(ctx, pairs, count, alphabet, flags, tuning, out);
+}
+
+// Enqueue the whole pass.  ev (optional) receives: before prep, before
+// fill, after fill, after traceback.
+static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
+    const Plan &p = b->plan;
+    PrepArgs pa{};
+    pa.lut = b->lut;
+    pa.xbytes = b->xbytes;
+    pa.xcodes = b->xcodes;
+    pa.xarena = b->xarena;
+    pa.ybytes = b->ybytes;
+    pa.seg_yoff = b->seg_yoff;
+    pa.seg_n = b->seg_n;
+    pa.seg_begin = b->seg_begin;
+    pa.seg_pre = b->seg_pre;
+    pa.seg_len = b->seg_len;
+    pa.seg_shift = b->seg_shift;
+    pa.nseg = (uint32_t)p.segs.size();
+    pa.ystream = b->ystream;
+    pa.sentinel = (uint32_t)b->sigma;
+    pa.out_len = b->out_len;
+    pa.npairs = (uint32_t)b->npairs;
+    pa.zero_words = b->zero;
+    pa.nzero = b->nzero;
+    if (events) HIP_TRY(hipEventRecord(b->ev[0], s));
+    HIP_TRY(launch_prep(pa, b->xarena + 64, s));
+    if (events) HIP_TRY(hipEventRecord(b->ev[1], s));
+    const bool tb = (b->flags & LCS_WANT_TRACEBACK) != 0;
+    auto fill_args = [&](size_t ci) {
+        const ClassDev &D = b->cls[ci];
+        FillArgs fa{};
+        fa.xcodes = b->xcodes;
+        fa.pair_xoff = b->pair_xoff;
+        fa.pair_m = b->pair_m;
+        fa.ystream = b->ystream;
+        fa.it_T = D.it_T;
+        fa.it_prev = D.it_prev;
+        fa.it_feeds = D.it_feeds;
+        fa.it_ck = D.it_ck;
+        fa.it_cb = D.it_cb;
+        fa.it_xf = D.it_xf;
+        fa.ln_pair = D.ln_pair;
+        fa.ln_word0 = D.ln_word0;
+        fa.ln_skew = D.ln_skew;
+        fa.ln_ys = D.ln_ys;
+        fa.out_len = b->out_len;
+        fa.ckpt = D.ckpt;
+        fa.cbits = D.cbits;
+        fa.xfer = D.xfer;
+        fa.progress = D.progress;
+        fa.queue = D.q_fill;
+        fa.error = b->error;
+        fa.item_begin = 0;
+        fa.item_end = D.nitems;
+        fa.spin_limit = b->spin_limit;
+        fa.sigma = b->sigma;
+        fa.ckpt_every = b->ckpt;
+        return fa;
+    };
+    auto tb_args = [&](size_t ci) {
+        const ClassDev &D = b->cls[ci];
+        TbArgs ta{};
+        ta.xcodes = b->xcodes;
+        ta.xbytes = b->xbytes;
+        ta.pair_xoff = b->pair_xoff;
+        ta.pair_m = b->pair_m;
+        ta.pair_n = b->pair_n;
+        ta.pair_out = b->pair_out;
+        ta.out_len = b->out_len;
+        ta.ystream = b->ystream;
+        ta.it_ck = D.it_ck;
+        ta.it_cb = D.it_cb;
+        ta.ln_skew = D.ln_skew;
+        ta.ln_ys = D.ln_ys;
+        ta.ckpt = D.ckpt;
+        ta.cbits = D.cbits;
+        ta.tb_pair = D.tb_pair;
+        ta.tb_item = D.tb_item;
+        ta.tb_lane0 = D.tb_lane0;
+        ta.ntb = D.ntb;
+        ta.out = b->out;
+        ta.queue = D.q_tb;
+        ta.sigma = b->sigma;
+        ta.ckpt_every = b->ckpt;
+        return ta;
+    };
+    if (!b->plain) {
+        for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+            const ClassDev &D = b->cls[ci];
+            if (!D.nitems) continue;
+            HIP_TRY(launch_fill(D.wpl, tb, fill_args(ci), D.fill_grid, s));
+        }
+        if (events) HIP_TRY(hipEventRecord(b->ev[2], s));
+        if (tb)
+            for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+                const ClassDev &D = b->cls[ci];
+                if (!D.ntb) continue;
+                HIP_TRY(launch_tb(D.wpl, tb_args(ci), D.tb_grid, s));
+            }
+    } else {
+        // plain per-pair: every pair gets its own fill launch (and its own
+        // traceback launch), in order
+        for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+            const ClassDev &D = b->cls[ci];
+            uint32_t *ctr = D.progress + D.nitems;
+            for (size_t k = 0; k < D.pl_pair.size(); ++k) {
+                FillArgs fa = fill_args(ci);
+                fa.item_begin = D.pl_begin[k];
+                fa.item_end = D.pl_end[k];
+                fa.queue = ctr + 2 * k;
+                uint32_t g = (fa.item_end - fa.item_begin + 3) / 4;
+                HIP_TRY(launch_fill(D.wpl, tb, fa, g, s));
+                if (tb) {
+                    TbArgs ta = tb_args(ci);
+                    ta.tb_pair = D.tb_pair + D.pl_tb[k];
+                    ta.tb_item = D.tb_item + D.pl_tb[k];
+                    ta.tb_lane0 = D.tb_lane0 + D.pl_tb[k];
+                    ta.ntb = 1;
+                    ta.queue = ctr + 2 * k + 1;
+                    HIP_TRY(launch_tb(D.wpl, ta, 1, s));
+                }
+            }
+        }
+        if (events) HIP_TRY(hipEventRecord(b->ev[2], s));
+    }
+    if (events) HIP_TRY(hipEventRecord(b->ev[3], s));
+    return LCS_OK;
+}
+
+// Launch one pass.  Graph batches capture the sequence once (with the HIP
+// event records as graph nodes, so per-pass timings stay readable) and replay
+// it; the others enqueue the kernels directly.
+static lcs_status launch_pass(lcs_batch *b) {
+    lcs_ctx *ctx = b->ctx;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
+    hipStream_t s = ctx->stream;
+    if ((b->flags & LCS_USE_GRAPH) && !b->plain) {
+        if (!b->gexec) {
+            for (int attempt = 0; attempt < 2 && !b->gexec; ++attempt) {
+                const bool with_events = attempt == 0;
+                HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                lcs_status st = enqueue(b, s, with_events);
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(s, &g);
+                if (st != LCS_OK || e != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    (void)hipGetLastError();
+                    if (attempt == 1) return st != LCS_OK ? st : dev_err(e);
+                    continue;
+                }
+                hipGraphExec_t ge = nullptr;
+                e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    (void)hipGraphDestroy(g);
+                    (void)hipGetLastError();
+                    if (attempt == 1) return dev_err(e);
+                    continue;
+                }
+                b->graph = g;
+                b->gexec = ge;
+                b->graph_events = with_events;
+            }
+        }
+        if (!b->graph_events) HIP_TRY(hipEventRecord(b->ev[0], s));
+        HIP_TRY(hipGraphLaunch(b->gexec, s));
+        if (!b->graph_events) HIP_TRY(hipEventRecord(b->ev[3], s));
+        b->timed_fill = b->graph_events;
+    } else {
+        lcs_status st = enqueue(b, s, true);
+        if (st) return st;
+        b->timed_fill = true;
+    }
+    b->ran = true;
+    return LCS_OK;
+}
+
+extern "C" lcs_status lcs_batch_run(lcs_batch *b) {
+    if (!b) return LCS_ERR_ARG;
+    return launch_pass(b);
+}
+
+static lcs_status finish(lcs_batch *b) {
+    if (!b->ran) return LCS_ERR_ARG;
+    lcs_ctx *ctx = b->ctx;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpy(&err, b->error, 4, hipMemcpyDeviceToHost));
+    if (err) return LCS_ERR_DEVICE;
+    return LCS_OK;
+}
+
+extern "C" lcs_status lcs_batch_lengths(lcs_batch *b, uint64_t *out_lens) {
+    if (!b || (b->npairs && !out_lens)) return LCS_ERR_ARG;
+    lcs_status st = finish(b);
+    if (st) return st;
+    if (b->npairs) HIP_TRY(hipMemcpy(out_lens, b->out_len, b->npairs * 8, hipMemcpyDeviceToHost));
+    return LCS_OK;
+}
+
+extern "C" lcs_status lcs_batch_tracebacks(lcs_batch *b, uint8_t *out_arena, uint64_t arena_cap,
+                                           uint64_t *out_offsets, uint64_t *out_lens) {
+    if (!b) return LCS_ERR_ARG;
+    if (!(b->flags & LCS_WANT_TRACEBACK)) return LCS_ERR_ARG;
+    if (b->npairs && (!out_offsets || !out_lens)) return LCS_ERR_ARG;
+    if (arena_cap < b->out_off_host[b->npairs]) return LCS_ERR_BUFFER;
+    if (b->out_off_host[b->npairs] && !out_arena) return LCS_ERR_ARG;
+    lcs_status st = finish(b);
+    if (st) return st;
+    std::vector<uint64_t> L(b->npairs);
+    std::vector<uint8_t> raw(b->out_bytes + 1);
+    if (b->npairs) HIP_TRY(hipMemcpy(L.data(), b->out_len, b->npairs * 8, hipMemcpyDeviceToHost));
+    if (b->out_bytes) HIP_TRY(hipMemcpy(raw.data(), b->out, b->out_bytes, hipMemcpyDeviceToHost));
+    uint64_t o = 0;
+    for (uint64_t k = 0; k < b->npairs; ++k) {
+        if (L[k] > std::min(b->m[k], b->n[k])) return LCS_ERR_DEVICE;
+        out_offsets[k] = o;
+        out_lens[k] = L[k];
+        if (L[k]) std::memcpy(out_arena + o, raw.data() + b->out_off_host[k], L[k]);
+        o += L[k];
+    }
+    return LCS_OK;
+}
+
+extern "C" lcs_status lcs_batch_info(const lcs_batch *b, lcs_batch_stats *out) {
+    if (!b || !out) return LCS_ERR_ARG;
+    stats_from_plan(b->plan, b->npairs, out);
+    out->device_bytes = b->dev_bytes;
+    out->flags = (int32_t)b->flags;
+    return LCS_OK;
+}
+
+extern "C" lcs_status lcs_batch_time(lcs_batch *b, float *total_ms, float *fill_ms) {
+    if (!b) return LCS_ERR_ARG;
+    lcs_status st = launch_pass(b);
+    if (st) return st;
+    st = finish(b);
+    if (st) return st;
+    float t = 0.f;
+    if (total_ms) {
+        HIP_TRY(hipEventElapsedTime(&t, b->ev[0], b->ev[3]));
+        *total_ms = t;
+    }
+    if (fill_ms) {
+        if (b->timed_fill) {
+            HIP_TRY(hipEventElapsedTime(&t, b->ev[1], b->ev[2]));
+            *fill_ms = t;
+        } else {
+            *fill_ms = -1.f;
+        }
+    }
+    return LCS_OK;
+}
+
+extern "C" void lcs_batch_destroy(lcs_batch *b) { free_batch(b); }
+
+// --------------------------------------------------------------------------
+// one-call entry points
+// --------------------------------------------------------------------------
+
+static const lcs_tuning kSinglePair = {1, 0, 0, 0};   // most lanes per pair
+
+extern "C" lcs_status lcs_length(lcs_ctx *ctx, const uint8_t *x, uint64_t m, const uint8_t *y,
+                                 uint64_t n, const lcs_alphabet *alphabet, uint64_t *out_len) {
+    if (!ctx || !out_len) return LCS_ERR_ARG;
+    lcs_pair p = {x, m, y, n};
+    lcs_tuning t = kSinglePair;
+    lcs_batch *b = nullptr;
+    lcs_status st = build_batch(ctx, &p, 1, alphabet, 0, &t, &b);
+    if (st) return st;
+    st = lcs_batch_run(b);
+    uint64_t L = 0;
+    if (!st) st = lcs_batch_lengths(b, &L);
+    free_batch(b);
+    if (!st) *out_len = L;
+    return st;
+}
+
+extern "C" lcs_status lcs_traceback(lcs_ctx *ctx, const uint8_t *x, uint64_t m, const uint8_t *y,
+                                    uint64_t n, const lcs_alphabet *alphabet, uint8_t *out,
+                                    uint64_t out_cap, uint64_t *out_len) {
+    if (!ctx || !out_len) return LCS_ERR_ARG;
+    if (out_cap < std::min(m, n)) return LCS_ERR_BUFFER;
+    if (std::min(m, n) && !out) return LCS_ERR_ARG;
+    lcs_pair p = {x, m, y, n};
+    lcs_tuning t = kSinglePair;
+    lcs_batch *b = nullptr;
+    lcs_status st = build_batch(ctx, &p, 1, alphabet, LCS_WANT_TRACEBACK, &t, &b);
+    if (st) return st;
+    st = lcs_batch_run(b);
+    uint64_t off = 0, L = 0;
+    if (!st) st = lcs_batch_tracebacks(b, out, out_cap, &off, &L);
+    free_batch(b);
+    if (!st) *out_len = L;
+    return st;
+}
+
+extern "C" lcs_status lcs_length_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                                       const lcs_alphabet *alphabet, uint64_t *out_lens) {
+    if (!ctx || (count && !out_lens)) return LCS_ERR_ARG;
+    lcs_batch *b = nullptr;
+    lcs_status st = build_batch(ctx, pairs, count, alphabet, 0, nullptr, &b);
+    if (st) return st;
+    st = lcs_batch_run(b);
+    if (!st) st = lcs_batch_lengths(b, out_lens);
+    free_batch(b);
+    return st;
+}
+
+extern "C" lcs_status lcs_traceback_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                                          const lcs_alphabet *alphabet, uint8_t *out_arena,
+                                          uint64_t arena_cap, uint64_t *out_offsets,
+                                          uint64_t *out_lens) {
+    if (!ctx || (count && (!out_offsets || !out_lens))) return LCS_ERR_ARG;
+    lcs_status st = check_pairs(pairs, count);
+    if (st) return st;
+    uint64_t worst = 0;
+    for (uint64_t k = 0; k < count; ++k) worst += std::min(pairs[k].m, pairs[k].n);
+    if (arena_cap < worst) return LCS_ERR_BUFFER;
+    if (worst && !out_arena) return LCS_ERR_ARG;
+    lcs_batch *b = nullptr;
+    st = build_batch(ctx, pairs, count, alphabet, LCS_WANT_TRACEBACK, nullptr, &b);
+    if (st) return st;
+    st = lcs_batch_run(b);
+    if (!st) st = lcs_batch_tracebacks(b, out_arena, arena_cap, out_offsets, out_lens);
+    free_batch(b);
+    return st;
+}
+
+// --------------------------------------------------------------------------
+// host-only planning checks
+// --------------------------------------------------------------------------
+
+static lcs_status plan_only(const uint64_t *m, const uint64_t *n, uint64_t count,
+                            uint16_t alphabet_size, uint32_t flags, const lcs_tuning *tuning,
+                            std::vector<PairShape> &shapes, Plan &plan) {
+    if (count && (!m || !n)) return LCS_ERR_ARG;
+    if (alphabet_size < 1 || alphabet_size > 256) return LCS_ERR_ARG;
+    if (flags & ~(uint32_t)(LCS_WANT_TRACEBACK | LCS_USE_GRAPH)) return LCS_ERR_ARG;
+    lcs_status st = check_tuning(tuning);
+    if (st) return st;
+    if (alphabet_size > 127 || max_wpl(alphabet_size) == 0) return LCS_ERR_UNSUPPORTED;
+    if (tuning && tuning->words_per_lane && !wpl_fits(alphabet_size, tuning->words_per_lane))
+        return LCS_ERR_UNSUPPORTED;
+    shapes.resize(count);
+    for (uint64_t k = 0; k < count; ++k) {
+        if (m[k] > LCS_MAX_LEN || n[k] > LCS_MAX_LEN) return LCS_ERR_TOO_LONG;
+        shapes[k].m = m[k];
+        shapes[k].n = n[k];
+    }
+    PlanConfig cfg;
+    fill_plan_config(cfg, alphabet_size, flags, tuning);
+    std::string why = build_plan(shapes, cfg, plan);
+    if (!why.empty()) {
+        if (why.find("longer") != std::string::npos || why.find("too long") != std::string::npos ||
+            why.find("too many") != std::string::npos)
+            return LCS_ERR_TOO_LONG;
+        return LCS_ERR_UNSUPPORTED;
+    }
+    return LCS_OK;
+}
+
+extern "C" lcs_status lcs_plan_describe(const uint64_t *m, const uint64_t *n, uint64_t count,
+                                        uint16_t alphabet_size, uint32_t flags,
+                                        const lcs_tuning *tuning, lcs_batch_stats *out) {
+    if (!out) return LCS_ERR_ARG;
+    std::vector<PairShape> shapes;
+    Plan plan;
+    lcs_status st = plan_only(m, n, count, alphabet_size, flags, tuning, shapes, plan);
+    if (st) return st;
+    stats_from_plan(plan, count, out);
+    return LCS_OK;
+}
+
+extern "C" lcs_status lcs_plan_selfcheck(const uint64_t *m, const uint64_t *n, uint64_t count,
+                                         uint16_t alphabet_size, uint32_t flags,
+                                         const lcs_tuning *tuning) {
+    std::vector<PairShape> shapes;
+    Plan plan;
+    lcs_status st = plan_only(m, n, count, alphabet_size, flags, tuning, shapes, plan);
+    if (st) return st;
+    std::string why = check_plan(shapes, plan);
+    if (!why.empty()) {
+        std::fprintf(stderr, "lcs_plan_selfcheck: %s\n", why.c_str());
+        return LCS_ERR_ARG;
+    }
+    return LCS_OK;
+}

@@ -1,0 +1,509 @@
+// lcs_kernels.hip -- gfx950 kernels of the LCS library.
+//
+// Bit-vector form of the dynamic program of section I.C.  For column j let
+// V_j be the m-bit vector whose bit (i-1) is 1 exactly when
+// c[i][j] == c[i-1][j].  Column 0 is all zero in c, so V_0 is all ones; with
+// PM_a the match mask of symbol a (bit (i-1) set when x_i == a), one column
+// step is the add-and-mask recurrence of Allison & Dix (1986) in the
+// four-operation form of Crochemore, Iliopoulos, Pinzon & Reid (2001):
+//
+//     U = V & PM[y_j]        V' = (V + U) | (V & ~PM[y_j])
+//
+// where "+" is an m-bit addition whose carries run from row 1 upward.  Then
+// c[i][j] = i - popcount(V_j & (2^i - 1)), so the LCS length c[m][n] is the
+// number of zero bits among the m valid bits of V_n.
+//
+// Mapping: a lane keeps WPL consecutive 64-bit words of V in registers; a
+// pair's words are spread over consecutive lanes.  Lane k of a pair works on
+// column (t - skew_k) at step t with skew growing by one per lane, so the
+// carry leaving lane k-1 for column j is produced one step before lane k
+// needs it: the carry hand-over is a shift of the wave's carry-out lane mask
+// (ballot) by one lane, fed back as the carry-in lane mask of the next step.
+// No cross-lane add is ever waited for inside a step.
+//
+// Traceback (section I.D with ties going up): at (i, j) a match moves
+// diagonally and emits x_i; otherwise c[i-1][j] >= c[i][j-1] holds exactly
+// when c[i-1][j] == c[i][j], i.e. when bit (i-1) of V_j is 1, and the walk
+// moves up; else it moves left.  Inside one column the walk therefore jumps
+// to the highest row r <= i with (PM[y_j] | ~V_j) set at r.  The fill stores
+// V every `ckpt_every` steps and every lane's carry-in bits, so any
+// (lane, step range) tile of the V history can be recomputed on its own;
+// the traceback recomputes only the tiles the path crosses.
+#include "kernels.hpp"
+
+namespace lcs {
+
+// --------------------------------------------------------------------------
+// prep: symbol remap (bytes -> codes), Y streams, zeroing
+// --------------------------------------------------------------------------
+
+__global__ void k_remap_x(const uint8_t *__restrict__ lut, const uint8_t *__restrict__ src,
+                          uint8_t *__restrict__ dst, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 4;
+    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i < n; i += stride) {
+        if (i + 4 <= n) {
+            uint32_t w = *(const uint32_t *)(src + i);
+            uint32_t r = (uint32_t)lut[w & 0xff] | ((uint32_t)lut[(w >> 8) & 0xff] << 8) |
+                         ((uint32_t)lut[(w >> 16) & 0xff] << 16) | ((uint32_t)lut[w >> 24] << 24);
+            *(uint32_t *)(dst + i) = r;
+        } else {
+            for (uint64_t k = i; k < n; ++k) dst[k] = lut[src[k]];
+        }
+    }
+}
+
+// One work-group per stream region (grid-stride over regions): codes of Y at
+// columns 0..n-1, the sentinel code everywhere else in the region, each
+// shifted into a byte offset of its row of match masks.
+__global__ void k_streams(PrepArgs a) {
+    for (uint32_t s = blockIdx.x; s < a.nseg; s += gridDim.x) {
+        const uint64_t begin = a.seg_begin[s];
+        const uint64_t len = a.seg_len[s];
+        const uint64_t pre = a.seg_pre[s];
+        const uint64_t n = a.seg_n[s];
+        const uint32_t sh = a.seg_shift[s];
+        const uint8_t *y = a.ybytes + a.seg_yoff[s];
+        const uint16_t sent = (uint16_t)(a.sentinel << sh);
+        for (uint64_t k = threadIdx.x; k < len; k += blockDim.x) {
+            uint16_t c = sent;
+            if (k >= pre && k - pre < n) c = (uint16_t)((uint32_t)a.lut[y[k - pre]] << sh);
+            a.ystream[begin + k] = c;
+        }
+    }
+}
+
+__global__ void k_zero(PrepArgs a) {
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = tid; k < a.npairs; k += stride) a.out_len[k] = 0;
+    for (uint64_t k = tid; k < a.nzero; k += stride) a.zero_words[k] = 0;
+}
+
+hipError_t launch_prep(const PrepArgs &a, uint64_t xbytes_n, hipStream_t s) {
+    if (xbytes_n) {
+        uint64_t blocks = (xbytes_n / 4 + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL(k_remap_x, dim3((uint32_t)blocks), dim3(256), 0, s, a.lut, a.xbytes,
+                           a.xcodes, xbytes_n);
+    }
+    hipLaunchKernelGGL(k_zero, dim3(512), dim3(256), 0, s, a);
+    if (a.nseg) {
+        uint32_t blocks = a.nseg < 65536 ? a.nseg : 65536;
+        hipLaunchKernelGGL(k_streams, dim3(blocks), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// fill
+// --------------------------------------------------------------------------
+
+size_t fill_lds_bytes(int wpl, int sigma) {
+    return (size_t)(kFillBlock / 64) * (size_t)(sigma + 1) * (size_t)wpl * 64 * sizeof(uint64_t);
+}
+
+// One column step for WPL words of one lane: U = V & M, S = V + U + carry
+// (64*WPL-bit add, carry in and out as a wave lane mask in an SGPR pair),
+// V' = S | (V & ~M).  Six VALU instructions per 64 cells.
+//
+// The carry mask is written by a VALU instruction (v_addc_co_u32) and read
+// by the next v_addc_co_u32; gfx950 needs two wait states between the two,
+// which the order below provides with independent instructions: inside a
+// word the low-half bitop3 and the high-half AND sit between the two adds;
+// across words the high-half bitop3 of the previous word and the low-half
+// AND of the next one do.  The carry mask coming in is always written by
+// scalar instructions and the one going out is only read by scalar
+// instructions, which need no wait states.
+template <int WPL>
+__device__ __forceinline__ void column_step(uint32_t (&vlo)[WPL], uint32_t (&vhi)[WPL],
+                                            const uint64_t (&M)[WPL], uint64_t &carry) {
+#pragma unroll
+    for (int q = 0; q < WPL; ++q) {
+        const uint32_t mlo = (uint32_t)M[q], mhi = (uint32_t)(M[q] >> 32);
+        uint32_t t0, t1;
+        asm("v_and_b32 %[ulo], %[vlo], %[mlo]\n\t"
+            "v_addc_co_u32 %[ulo], %[c], %[vlo], %[ulo], %[c]\n\t"
+            "v_bitop3_b32 %[vlo], %[ulo], %[vlo], %[mlo] bitop3:0xf4\n\t"
+            "v_and_b32 %[uhi], %[vhi], %[mhi]\n\t"
+            "v_addc_co_u32 %[uhi], %[c], %[vhi], %[uhi], %[c]\n\t"
+            "v_bitop3_b32 %[vhi], %[uhi], %[vhi], %[mhi] bitop3:0xf4"
+            : [vlo] "+v"(vlo[q]), [vhi] "+v"(vhi[q]), [c] "+s"(carry), [ulo] "=&v"(t0),
+              [uhi] "=&v"(t1)
+            : [mlo] "v"(mlo), [mhi] "v"(mhi));
+    }
+}
+
+// Y stream element: code * (WPL * 512), i.e. the byte offset of the code's
+// row of match masks in the wave's LDS block ([symbol][word][lane] layout).
+template <int WPL, bool TB>
+__global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
+    extern __shared__ uint64_t smem[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int sig1 = a.sigma + 1;
+    constexpr uint32_t RS = WPL * 64;            // words per symbol row
+    uint64_t *pm = smem + (size_t)wv * sig1 * RS;
+    // this lane's column of the wave's block; a stream value is a byte offset
+    const char *lanecol = (const char *)(pm + lane);
+
+    for (;;) {
+        uint32_t ticket = 0;
+        if (lane == 0) ticket = atomicAdd(a.queue, 1u);
+        ticket = __builtin_amdgcn_readfirstlane(ticket);
+        if (ticket >= a.item_end - a.item_begin) return;
+        const uint32_t item = a.item_begin + ticket;
+
+        const size_t li = (size_t)item * 64 + lane;
+        const int32_t pair = a.ln_pair[li];
+        const uint32_t word0 = a.ln_word0[li];
+        const uint32_t skew = a.ln_skew[li];
+        const uint64_t ysoff = a.ln_ys[li];
+        const uint32_t T = a.it_T[item];
+        const int32_t prev = a.it_prev[item];
+        const bool feeds = a.it_feeds[item] != 0;
+
+        // ---- match masks of this lane's rows (LDS, own column only) ----
+        for (int c = 0; c < sig1; ++c)
+#pragma unroll
+            for (int q = 0; q < WPL; ++q) pm[c * RS + q * 64 + lane] = 0;
+        uint32_t m = 0;
+        if (pair >= 0) {
+            m = a.pair_m[pair];
+            const uint8_t *xc = a.xcodes + a.pair_xoff[pair];
+            for (int q = 0; q < WPL; ++q) {
+                const uint32_t row0 = (word0 + q) * 64u;
+                if (row0 >= m) break;
+                uint64_t *col = pm + q * 64 + lane;
+                const uint32_t cnt = (m - row0) < 64u ? (m - row0) : 64u;
+#pragma unroll 1
+                for (uint32_t r0 = 0; r0 < cnt; r0 += 4) {
+                    // the X arena is padded to 64 bytes per sequence
+                    const uint32_t w4 = *(const uint32_t *)(xc + row0 + r0);
+#pragma unroll
+                    for (int by = 0; by < 4; ++by) {
+                        const uint32_t r = r0 + by;
+                        if (r < cnt) {
+                            const uint32_t c = (w4 >> (8 * by)) & 0xffu;
+                            atomicOr((unsigned long long *)(col + c * RS), 1ull << r);
+                        }
+                    }
+                }
+            }
+        }
+
+        // ---- column steps ----
+        uint32_t vlo[WPL], vhi[WPL];
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) { vlo[q] = ~0u; vhi[q] = ~0u; }
+        const uint16_t *ys = a.ystream + ysoff - skew;
+        const uint64_t startmask = __builtin_amdgcn_ballot_w64(pair < 0 || word0 == 0);
+        const uint64_t notstart = ~startmask;
+        uint64_t cmask = 0;
+        uint32_t acc = 0;
+        const uint32_t nch = T / 64;
+        uint64_t *ckp = nullptr;
+        uint32_t *cbp = nullptr;
+        if (TB) {
+            ckp = a.ckpt + a.it_ck[item] + lane;
+            cbp = a.cbits + a.it_cb[item] + lane;
+        }
+        uint64_t *xf_out = feeds ? a.xfer + a.it_xf[item] : nullptr;
+        const uint64_t *xf_in = prev >= 0 ? a.xfer + a.it_xf[prev] : nullptr;
+        bool aborted = false;
+        // stream values for the next 8 steps, two per dword
+        uint32_t yw[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) yw[e] = (uint32_t)ys[2 * e] | ((uint32_t)ys[2 * e + 1] << 16);
+
+        for (uint32_t c = 0; c < nch; ++c) {
+            uint64_t inbits = 0;
+            if (prev >= 0 && c > 0) {
+                // bounded wait for the feeding item to finish chunk c-1
+                uint32_t spins = 0;
+                for (;;) {
+                    uint32_t got = __hip_atomic_load(a.progress + prev, __ATOMIC_ACQUIRE,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                    got = __builtin_amdgcn_readfirstlane(got);
+                    if (got >= c) break;
+                    if (++spins > a.spin_limit) { aborted = true; break; }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                if (aborted) break;
+                const uint64_t w = __hip_atomic_load(xf_in + (c - 1), __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)w);
+                const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(w >> 32));
+                inbits = ((uint64_t)hi << 32) | lo;
+            }
+            if (TB && ((c * 64u) % (uint32_t)a.ckpt_every) == 0) {
+                uint64_t *dst = ckp + (size_t)((c * 64u) / (uint32_t)a.ckpt_every) * RS;
+#pragma unroll
+                for (int q = 0; q < WPL; ++q) dst[q * 64] = ((uint64_t)vhi[q] << 32) | vlo[q];
+            }
+            uint64_t outbits = 0;
+#pragma unroll 1
+            for (int g = 0; g < 8; ++g) {
+                const uint32_t t = c * 64u + (uint32_t)g * 8u;
+                uint32_t yn[4];
+                const uint16_t *nx = ys + t + 8;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    yn[e] = (uint32_t)nx[2 * e] | ((uint32_t)nx[2 * e + 1] << 16);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t off = (e & 1) ? (yw[e >> 1] >> 16) : (yw[e >> 1] & 0xffffu);
+                    const char *row = lanecol + off;
+                    uint64_t M[WPL];
+#pragma unroll
+                    for (int q = 0; q < WPL; ++q) M[q] = *(const uint64_t *)(row + q * 512);
+                    uint64_t cm = cmask | (inbits & 1ull);
+                    inbits >>= 1;
+                    if (TB) {
+                        uint32_t cj;
+                        acc = __builtin_addc(acc, acc,
+                                             (uint32_t)__builtin_amdgcn_inverse_ballot_w64(cm), &cj);
+                        if ((e & 7) == 7 && (g & 3) == 3)
+                            cbp[(size_t)((t + e) >> 5) * 64] = acc;
+                    }
+                    column_step<WPL>(vlo, vhi, M, cm);
+                    outbits = (outbits >> 1) | (cm & 0x8000000000000000ull);
+                    cmask = (cm << 1) & notstart;
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) yw[e] = yn[e];
+            }
+            if (feeds && lane == 0) {
+                xf_out[c] = outbits;
+                __hip_atomic_store(a.progress + item, c + 1, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (aborted) {
+            if (lane == 0) atomicOr(a.error, 1u);
+            return;
+        }
+
+        // ---- length: zero bits among the valid rows ----
+        if (pair >= 0) {
+            uint32_t zeros = 0;
+#pragma unroll
+            for (int q = 0; q < WPL; ++q) {
+                const uint32_t row0 = (word0 + q) * 64u;
+                if (row0 < m) {
+                    const uint32_t cnt = (m - row0) < 64u ? (m - row0) : 64u;
+                    const uint64_t mask = cnt == 64u ? ~0ull : ((1ull << cnt) - 1);
+                    const uint64_t v = ((uint64_t)vhi[q] << 32) | vlo[q];
+                    zeros += cnt - (uint32_t)__builtin_popcountll(v & mask);
+                }
+            }
+            if (zeros) atomicAdd((unsigned long long *)(a.out_len + pair), (unsigned long long)zeros);
+        }
+    }
+}
+
+const void *fill_symbol(int wpl, bool tb) {
+    switch (wpl) {
+        case 1: return tb ? (const void *)&k_fill<1, true> : (const void *)&k_fill<1, false>;
+        case 2: return tb ? (const void *)&k_fill<2, true> : (const void *)&k_fill<2, false>;
+        case 4: return tb ? (const void *)&k_fill<4, true> : (const void *)&k_fill<4, false>;
+        default: return tb ? (const void *)&k_fill<8, true> : (const void *)&k_fill<8, false>;
+    }
+}
+
+hipError_t launch_fill(int wpl, bool tb, const FillArgs &a, uint32_t grid, hipStream_t s) {
+    const size_t lds = fill_lds_bytes(wpl, a.sigma);
+#define LCS_FILL_CASE(W)                                                                  \
+    case W:                                                                               \
+        if (tb)                                                                           \
+            hipLaunchKernelGGL((k_fill<W, true>), dim3(grid), dim3(kFillBlock), lds, s, a); \
+        else                                                                              \
+            hipLaunchKernelGGL((k_fill<W, false>), dim3(grid), dim3(kFillBlock), lds, s, a); \
+        break;
+    switch (wpl) {
+        LCS_FILL_CASE(1)
+        LCS_FILL_CASE(2)
+        LCS_FILL_CASE(4)
+        LCS_FILL_CASE(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef LCS_FILL_CASE
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// traceback
+// --------------------------------------------------------------------------
+
+__host__ __device__ static inline size_t tb_wave_words(int wpl, int sigma, int K) {
+    // match masks of one band, the V history of one tile, the tile's codes
+    return (size_t)(sigma + 1) * wpl + (size_t)K * wpl + ((size_t)K + 7) / 8;
+}
+
+size_t tb_lds_bytes(int wpl, int sigma, int K) {
+    return (size_t)(kTbBlock / 64) * tb_wave_words(wpl, sigma, K) * sizeof(uint64_t);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int WPL>
+__global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
+    extern __shared__ uint64_t smem[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int sig1 = a.sigma + 1;
+    const uint32_t K = (uint32_t)a.ckpt_every;
+    uint64_t *pmw = smem + (size_t)wv * tb_wave_words(WPL, a.sigma, (int)K);
+    uint64_t *tv = pmw + sig1 * WPL;
+    uint8_t *ty = (uint8_t *)(tv + (size_t)K * WPL);
+    const uint32_t BAND = 64u * WPL;
+    constexpr uint32_t kShift = 9 + (WPL == 1 ? 0 : WPL == 2 ? 1 : WPL == 4 ? 2 : 3);
+
+    for (;;) {
+        uint32_t ticket = 0;
+        if (lane == 0) ticket = atomicAdd(a.queue, 1u);
+        ticket = __builtin_amdgcn_readfirstlane(ticket);
+        if (ticket >= a.ntb) return;
+        const uint32_t p = a.tb_pair[ticket];
+        const uint32_t item0 = a.tb_item[ticket];
+        const uint32_t lane0 = a.tb_lane0[ticket];
+        const uint32_t m = a.pair_m[p];
+        const uint32_t n = a.pair_n[p];
+        int64_t k = (int64_t)a.out_len[p];
+        const uint8_t *xc = a.xcodes + a.pair_xoff[p];
+        const uint8_t *xb = a.xbytes + a.pair_xoff[p];
+        uint8_t *out = a.out + a.pair_out[p];
+
+        int64_t i = m, j = n;
+        int64_t band = -1, tile = -1;
+        uint32_t skew = 0, lanei = 0;
+        const uint16_t *ys = nullptr;
+        const uint64_t *ck = nullptr;
+        const uint32_t *cb = nullptr;
+
+        while (i > 0 && j > 0) {
+            const int64_t ell = (i - 1) / BAND;
+            if (ell != band) {
+                band = ell;
+                tile = -1;
+                const uint32_t g = lane0 + (uint32_t)ell;
+                const uint32_t item = item0 + g / 64;
+                lanei = g % 64;
+                const size_t li = (size_t)item * 64 + lanei;
+                skew = a.ln_skew[li];
+                ys = a.ystream + a.ln_ys[li] - skew;
+                ck = a.ckpt + a.it_ck[item] + lanei;
+                cb = a.cbits + a.it_cb[item] + lanei;
+                // match masks of this band's rows
+                for (int e = lane; e < sig1 * WPL; e += 64) pmw[e] = 0;
+                wave_lds_sync();
+                const uint32_t rb = (uint32_t)ell * BAND;
+                for (uint32_t r = lane; r < BAND; r += 64) {
+                    const uint32_t row = rb + r;
+                    if (row < m) {
+                        const uint32_t c = xc[row];
+                        atomicOr((unsigned long long *)(pmw + c * WPL + r / 64), 1ull << (r % 64));
+                    }
+                }
+                wave_lds_sync();
+            }
+            const int64_t t = (j - 1) + (int64_t)skew;
+            const int64_t kt = t / K;
+            if (kt != tile) {
+                // recompute V for steps kt*K .. t of this lane from its checkpoint
+                uint64_t V[WPL];
+#pragma unroll
+                for (int q = 0; q < WPL; ++q) V[q] = ck[((size_t)kt * WPL + q) * 64];
+                const uint32_t t0 = (uint32_t)(kt * K);
+                for (uint32_t tt = t0; tt <= (uint32_t)t; ++tt) {
+                    const uint32_t y = (uint32_t)ys[tt] >> kShift;
+                    uint32_t carry = (cb[(size_t)(tt >> 5) * 64] >> (31 - (tt & 31))) & 1u;
+#pragma unroll
+                    for (int q = 0; q < WPL; ++q) {
+                        const uint64_t M = pmw[y * WPL + q];
+                        const uint64_t v = V[q];
+                        const uint64_t U = v & M;
+                        uint32_t c1, c2;
+                        const uint32_t slo = __builtin_addc((uint32_t)v, (uint32_t)U, carry, &c1);
+                        const uint32_t shi =
+                            __builtin_addc((uint32_t)(v >> 32), (uint32_t)(U >> 32), c1, &c2);
+                        carry = c2;
+                        V[q] = ((((uint64_t)shi) << 32) | slo) | (v & ~M);
+                    }
+                    if (lane == 0) {
+#pragma unroll
+                        for (int q = 0; q < WPL; ++q) tv[(size_t)(tt - t0) * WPL + q] = V[q];
+                        ty[tt - t0] = (uint8_t)y;
+                    }
+                }
+                wave_lds_sync();
+                tile = kt;
+            }
+            // walk inside the tile
+            int64_t tc = t;
+            const int64_t tlo = kt * K;
+            for (;;) {
+                const uint32_t o = (uint32_t)(tc - tlo);
+                const uint32_t y = ty[o];
+                const uint32_t rl = (uint32_t)((i - 1) - ell * BAND);
+                int q = (int)(rl / 64);
+                int b = (int)(rl % 64);
+                bool found = false;
+                uint64_t Mw = 0, cand = 0;
+                for (;;) {
+                    Mw = pmw[y * WPL + q];
+                    const uint64_t Vw = tv[(size_t)o * WPL + q];
+                    const uint64_t low = (b == 63) ? ~0ull : ((2ull << b) - 1);
+                    cand = (Mw | ~Vw) & low;
+                    if (cand) { found = true; break; }
+                    if (q == 0) break;
+                    --q;
+                    b = 63;
+                }
+                if (!found) {  // up through the rest of the band in column j
+                    i = ell * BAND;
+                    break;
+                }
+                const int r = 63 - __builtin_clzll(cand);
+                const int64_t row = ell * BAND + (int64_t)q * 64 + r + 1;
+                if ((Mw >> r) & 1ull) {
+                    --k;
+                    if (lane == 0 && k >= 0) out[k] = xb[row - 1];
+                    i = row - 1;
+                } else {
+                    i = row;
+                }
+                --j;
+                --tc;
+                if (i == 0 || j == 0) break;
+                if ((i - 1) / BAND != ell) break;
+                if (tc < tlo) break;
+            }
+        }
+    }
+}
+
+const void *tb_symbol(int wpl) {
+    switch (wpl) {
+        case 1: return (const void *)&k_traceback<1>;
+        case 2: return (const void *)&k_traceback<2>;
+        case 4: return (const void *)&k_traceback<4>;
+        default: return (const void *)&k_traceback<8>;
+    }
+}
+
+hipError_t launch_tb(int wpl, const TbArgs &a, uint32_t grid, hipStream_t s) {
+    const size_t lds = tb_lds_bytes(wpl, a.sigma, a.ckpt_every);
+    switch (wpl) {
+        case 1: hipLaunchKernelGGL((k_traceback<1>), dim3(grid), dim3(kTbBlock), lds, s, a); break;
+        case 2: hipLaunchKernelGGL((k_traceback<2>), dim3(grid), dim3(kTbBlock), lds, s, a); break;
+        case 4: hipLaunchKernelGGL((k_traceback<4>), dim3(grid), dim3(kTbBlock), lds, s, a); break;
+        case 8: hipLaunchKernelGGL((k_traceback<8>), dim3(grid), dim3(kTbBlock), lds, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lcs

@@ -1,0 +1,358 @@
+// plan.cpp -- packing of LCS pairs into wave-sized work items (see plan.hpp).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstdio>
+#include <numeric>
+
+namespace lcs {
+
+static inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Words-per-lane chosen automatically from the number of 64-bit words of a
+// pair: short columns keep all lanes busy with one word each; long columns
+// amortise the per-step overhead over more words per lane.
+//
+// Limits from the kernel: a stream element (code << log2(wpl*512)) must fit
+// 16 bits, so sigma * wpl <= 127; and four waves' match masks, 4 * (sigma+1)
+// * wpl * 512 bytes of LDS, should leave room for a second work-group on the
+// compute unit, so (sigma+1) * wpl <= 40 when possible.
+int max_wpl(int sigma) {
+    for (int w = 8; w >= 1; w >>= 1)
+        if ((sigma + 1) * w <= 40 && sigma * w <= 127) return w;
+    return (sigma * 1 <= 127 && (sigma + 1) * 4 * 512 * 1 <= 160 * 1024) ? 1 : 0;
+}
+
+bool wpl_fits(int sigma, int wpl) {
+    return sigma * wpl <= 127 && (size_t)4 * (sigma + 1) * wpl * 512 <= 160 * 1024;
+}
+
+static int auto_wpl(uint64_t W, int sigma) {
+    int w = W <= 8 ? 1 : (W <= 32 ? 2 : 4);
+    int mw = max_wpl(sigma);
+    return w < mw ? w : mw;
+}
+
+std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cfg, Plan &out) {
+    out = Plan();
+    out.cfg = cfg;
+    if (cfg.wpl != 0 && cfg.wpl != 1 && cfg.wpl != 2 && cfg.wpl != 4 && cfg.wpl != 8)
+        return "words_per_lane must be 1, 2, 4 or 8";
+    if (cfg.traceback && (cfg.ckpt <= 0 || cfg.ckpt % kChunk != 0))
+        return "ckpt_interval must be a positive multiple of 64";
+    const size_t np = pairs.size();
+    out.pair_class.assign(np, UINT32_MAX);
+
+    // assign pairs to classes by words-per-lane
+    int class_of_wpl[9];
+    for (int &c : class_of_wpl) c = -1;
+    std::vector<std::vector<uint32_t>> members;
+    for (size_t k = 0; k < np; ++k) {
+        const PairShape &p = pairs[k];
+        out.cells += p.m * p.n;
+        if (p.m == 0 || p.n == 0) continue;
+        uint64_t W = ceil_div(p.m, 64);
+        int wpl = cfg.wpl ? cfg.wpl : auto_wpl(W, cfg.sigma);
+        if (wpl == 0 || !wpl_fits(cfg.sigma, wpl)) return "alphabet too large for words_per_lane";
+        if (p.m > max_rows(wpl)) return "sequence X longer than the supported row count";
+        if (p.n > 0x7fffffffull) return "sequence Y too long";
+        if (class_of_wpl[wpl] < 0) {
+            class_of_wpl[wpl] = (int)out.classes.size();
+            out.classes.emplace_back();
+            out.classes.back().wpl = wpl;
+            members.emplace_back();
+        }
+        out.pair_class[k] = (uint32_t)class_of_wpl[wpl];
+        members[class_of_wpl[wpl]].push_back((uint32_t)k);
+    }
+
+    // Y stream: a leading all-sentinel region read by idle lanes; its length
+    // is fixed once max_T is known, so regions are laid out afterwards.
+    struct PendingSeg { uint32_t pair; uint32_t pre; uint32_t last_item; uint32_t cls; };
+    std::vector<PendingSeg> pend;
+
+    for (size_t ci = 0; ci < out.classes.size(); ++ci) {
+        ClassPlan &C = out.classes[ci];
+        const int wpl = C.wpl;
+        std::vector<uint32_t> &mem = members[ci];
+        std::stable_sort(mem.begin(), mem.end(), [&](uint32_t a, uint32_t b) {
+            if (pairs[a].n != pairs[b].n) return pairs[a].n > pairs[b].n;
+            return pairs[a].m > pairs[b].m;
+        });
+        int64_t cur_item = -1;
+        int cur_lane = kLanes;
+        // segments of each item, to set T afterwards
+        std::vector<std::vector<uint32_t>> item_segs;   // indices into pend
+        auto new_item = [&](int32_t prev) {
+            C.it_T.push_back(0);
+            C.it_prev.push_back(prev);
+            C.it_feeds.push_back(0);
+            for (int l = 0; l < kLanes; ++l) {
+                C.ln_pair.push_back(-1);
+                C.ln_word0.push_back(0);
+                C.ln_skew.push_back(0);
+                C.ln_ys.push_back(0);
+            }
+            item_segs.emplace_back();
+            return (int64_t)C.it_T.size() - 1;
+        };
+        for (uint32_t k : mem) {
+            const PairShape &p = pairs[k];
+            const uint64_t W = ceil_div(p.m, 64);
+            const uint64_t s = ceil_div(W, (uint64_t)wpl);
+            const uint32_t seg_id = (uint32_t)pend.size();
+            if (s <= (uint64_t)kLanes) {
+                if (cur_item < 0 || cur_lane + (int)s > kLanes || (cfg.plain && cur_lane > 0)) {
+                    cur_item = new_item(-1);
+                    cur_lane = 0;
+                }
+                for (uint64_t l = 0; l < s; ++l) {
+                    size_t li = (size_t)cur_item * kLanes + cur_lane + l;
+                    C.ln_pair[li] = (int32_t)k;
+                    C.ln_word0[li] = (uint32_t)(l * wpl);
+                    C.ln_skew[li] = (uint32_t)l;
+                }
+                C.tb_pair.push_back(k);
+                C.tb_item.push_back((uint32_t)cur_item);
+                C.tb_lane0.push_back((uint32_t)cur_lane);
+                pend.push_back({k, (uint32_t)(s - 1), (uint32_t)cur_item, (uint32_t)ci});
+                item_segs[cur_item].push_back(seg_id);
+                cur_lane += (int)s;
+            } else {
+                const uint64_t H = ceil_div(s, kLanes);
+                int64_t first = -1, prev = -1;
+                for (uint64_t h = 0; h < H; ++h) {
+                    int64_t it = new_item((int32_t)prev);
+                    if (h == 0) first = it;
+                    if (prev >= 0) C.it_feeds[prev] = 1;
+                    uint64_t nl = std::min<uint64_t>(kLanes, s - h * kLanes);
+                    for (uint64_t l = 0; l < nl; ++l) {
+                        size_t li = (size_t)it * kLanes + l;
+                        uint64_t pos = h * kLanes + l;
+                        C.ln_pair[li] = (int32_t)k;
+                        C.ln_word0[li] = (uint32_t)(pos * wpl);
+                        C.ln_skew[li] = (uint32_t)(h * (kLanes + kChunk) + l);
+                    }
+                    item_segs[it].push_back(seg_id);
+                    prev = it;
+                    cur_item = it;
+                    cur_lane = (int)nl;
+                }
+                uint64_t last_pos = s - 1;
+                uint64_t hl = last_pos / kLanes;
+                uint32_t pre = (uint32_t)(hl * (kLanes + kChunk) + (last_pos % kLanes));
+                C.tb_pair.push_back(k);
+                C.tb_item.push_back((uint32_t)first);
+                C.tb_lane0.push_back(0);
+                pend.push_back({k, pre, (uint32_t)cur_item, (uint32_t)ci});
+                if (cfg.plain) cur_lane = kLanes;
+            }
+        }
+        // steps per item: every segment in it must reach column n at its
+        // largest skew; chains share one step count
+        const size_t nit = C.it_T.size();
+        std::vector<uint64_t> T(nit, 0);
+        for (size_t it = 0; it < nit; ++it)
+            for (uint32_t sid : item_segs[it]) {
+                const PendingSeg &ps = pend[sid];
+                T[it] = std::max<uint64_t>(T[it], pairs[ps.pair].n + ps.pre + 1);
+            }
+        // propagate the maximum along chains (backwards then forwards)
+        for (size_t it = nit; it-- > 1;)
+            if (C.it_prev[it] >= 0) T[it - 1] = std::max(T[it - 1], T[it]);
+        for (size_t it = 1; it < nit; ++it)
+            if (C.it_prev[it] >= 0) T[it] = std::max(T[it], T[it - 1]);
+        for (size_t it = 0; it < nit; ++it) {
+            uint64_t t = ceil_div(std::max<uint64_t>(T[it], 1), kChunk) * kChunk;
+            if (t > 0xffffffffull - kChunk) return "too many steps for one work item";
+            C.it_T[it] = (uint32_t)t;
+            out.max_T = std::max<uint64_t>(out.max_T, t);
+            C.max_T = std::max<uint64_t>(C.max_T, t);
+            C.lane_steps += t * kLanes;
+        }
+        // traceback and hand-over storage
+        for (size_t it = 0; it < nit; ++it) {
+            uint64_t t = C.it_T[it];
+            C.it_ck.push_back(C.ck_words);
+            C.it_cb.push_back(C.cb_words);
+            C.it_xf.push_back(C.xf_words);
+            if (cfg.traceback) {
+                C.ck_words += ceil_div(t, (uint64_t)cfg.ckpt) * (uint64_t)wpl * kLanes;
+                C.cb_words += (t / kCbitsPer) * kLanes;
+            }
+            if (C.it_feeds[it]) C.xf_words += t / kChunk;
+        }
+        // traceback order: largest m*n first
+        std::vector<size_t> ord(C.tb_pair.size());
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+            return pairs[C.tb_pair[a]].m * pairs[C.tb_pair[a]].n >
+                   pairs[C.tb_pair[b]].m * pairs[C.tb_pair[b]].n;
+        });
+        std::vector<uint32_t> tp, ti, tl;
+        for (size_t o : ord) {
+            tp.push_back(C.tb_pair[o]); ti.push_back(C.tb_item[o]); tl.push_back(C.tb_lane0[o]);
+        }
+        C.tb_pair.swap(tp); C.tb_item.swap(ti); C.tb_lane0.swap(tl);
+        out.items += nit;
+        out.lanes += nit * kLanes;
+        out.lane_steps += C.lane_steps;
+    }
+
+    // lay out the Y stream: one all-sentinel region per class, then one
+    // region per segment
+    auto shift_of = [](int wpl) { return (uint8_t)(9 + (wpl == 1 ? 0 : wpl == 2 ? 1 : wpl == 4 ? 2 : 3)); };
+    uint64_t cursor = 0;
+    std::vector<uint64_t> class_sent(out.classes.size(), 0);
+    for (size_t ci = 0; ci < out.classes.size(); ++ci) {
+        const ClassPlan &C = out.classes[ci];
+        Segment sg;
+        sg.pair = kNoPair;
+        sg.pre = 0;
+        sg.begin = cursor;
+        sg.len = C.max_T + kChunk;
+        sg.shift = shift_of(C.wpl);
+        class_sent[ci] = cursor;
+        cursor += (sg.len + 63) / 64 * 64;
+        out.segs.push_back(sg);
+    }
+    std::vector<uint64_t> seg_col0(np, 0);
+    for (const PendingSeg &ps : pend) {
+        const ClassPlan &C = out.classes[ps.cls];
+        Segment sg;
+        sg.pair = ps.pair;
+        sg.pre = ps.pre;
+        sg.begin = cursor;
+        // + one chunk: the fill reads the stream a few steps ahead
+        sg.len = (uint64_t)ps.pre + C.it_T[ps.last_item] + kChunk;
+        sg.shift = shift_of(C.wpl);
+        cursor += (sg.len + 63) / 64 * 64;
+        seg_col0[ps.pair] = sg.begin + sg.pre;
+        out.segs.push_back(sg);
+    }
+    out.ys_elems = cursor;
+    // lane offsets into the stream
+    for (size_t ci = 0; ci < out.classes.size(); ++ci) {
+        ClassPlan &C = out.classes[ci];
+        for (size_t li = 0; li < C.ln_pair.size(); ++li)
+            C.ln_ys[li] = C.ln_pair[li] >= 0 ? seg_col0[C.ln_pair[li]] : class_sent[ci];
+    }
+    return std::string();
+}
+
+std::string check_plan(const std::vector<PairShape> &pairs, const Plan &p) {
+    char buf[256];
+    const size_t np = pairs.size();
+    std::vector<int> seen(np, 0);
+    std::vector<int64_t> seg_of(np, -1);
+    for (size_t si = 0; si < p.segs.size(); ++si) {
+        if (p.segs[si].pair == kNoPair) continue;
+        if (p.segs[si].pair >= np) return "segment pair out of range";
+        if (seg_of[p.segs[si].pair] >= 0) return "two stream regions for one pair";
+        seg_of[p.segs[si].pair] = (int64_t)si;
+    }
+    for (size_t ci = 0; ci < p.classes.size(); ++ci) {
+        const ClassPlan &C = p.classes[ci];
+        const size_t nit = C.it_T.size();
+        if (C.ln_pair.size() != nit * kLanes) return "lane table size";
+        for (size_t it = 0; it < nit; ++it) {
+            if (C.it_T[it] % kChunk) return "T not a multiple of the chunk";
+            if (C.it_prev[it] >= 0 && C.it_prev[it] != (int32_t)it - 1) return "chain not consecutive";
+            if (C.it_prev[it] >= 0 && !C.it_feeds[it - 1]) return "chain feed flag";
+            if (C.it_prev[it] >= 0 && C.it_T[it] != C.it_T[it - 1]) return "chain step counts differ";
+            for (int l = 0; l < kLanes; ++l) {
+                size_t li = it * kLanes + l;
+                int32_t pr = C.ln_pair[li];
+                if (pr < 0) continue;
+                if ((size_t)pr >= np) return "pair index out of range";
+                const PairShape &ps = pairs[pr];
+                uint64_t W = (ps.m + 63) / 64;
+                uint64_t word0 = C.ln_word0[li];
+                if (word0 >= W) return "lane holds no word of its pair";
+                if (word0 % C.wpl) return "word offset not aligned";
+                // the lane below holds the previous words of the same pair,
+                // either in this item or in lane 63 of the previous item
+                if (word0 > 0) {
+                    int32_t below_pair;
+                    uint32_t below_word0, below_skew;
+                    if (l > 0) {
+                        below_pair = C.ln_pair[li - 1];
+                        below_word0 = C.ln_word0[li - 1];
+                        below_skew = C.ln_skew[li - 1];
+                        if (C.ln_skew[li] != below_skew + 1) return "skew step inside an item";
+                    } else {
+                        if (C.it_prev[it] < 0) return "continuation without a feeding item";
+                        size_t lb = (it - 1) * kLanes + kLanes - 1;
+                        below_pair = C.ln_pair[lb];
+                        below_word0 = C.ln_word0[lb];
+                        below_skew = C.ln_skew[lb];
+                        if (C.ln_skew[li] != below_skew + 1 + kChunk) return "skew step across items";
+                    }
+                    if (below_pair != pr || below_word0 + C.wpl != word0) return "segment not contiguous";
+                } else {
+                    if (C.ln_skew[li] != 0) return "segment start with non-zero skew";
+                    seen[pr] += 1;
+                }
+                // every column reached before the item ends
+                if ((uint64_t)C.ln_skew[li] + ps.n > C.it_T[it]) {
+                    snprintf(buf, sizeof buf, "item %zu lane %d too few steps", it, l);
+                    return buf;
+                }
+                // stream reads stay inside the segment's region
+                if (seg_of[pr] < 0) return "segment without a stream region";
+                const Segment &sg = p.segs[seg_of[pr]];
+                if (C.ln_ys[li] != sg.begin + sg.pre) return "stream offset";
+                if (C.ln_skew[li] > sg.pre) return "skew beyond the pre-pad";
+                if ((uint64_t)sg.pre + C.it_T[it] + kChunk > sg.len) return "stream region too short";
+            }
+            // the lane of the pair with the highest word must be the last of
+            // its segment: a lane above it holding the same pair is an error
+        }
+    }
+    for (size_t k = 0; k < np; ++k) {
+        bool empty = pairs[k].m == 0 || pairs[k].n == 0;
+        if (empty && seen[k] != 0) return "empty pair scheduled";
+        if (!empty && seen[k] != 1) {
+            snprintf(buf, sizeof buf, "pair %zu scheduled %d times", k, seen[k]);
+            return buf;
+        }
+    }
+    // every word of every pair is held by exactly one lane
+    std::vector<uint64_t> words(np, 0);
+    for (const ClassPlan &C : p.classes)
+        for (size_t li = 0; li < C.ln_pair.size(); ++li)
+            if (C.ln_pair[li] >= 0) {
+                const PairShape &ps = pairs[C.ln_pair[li]];
+                uint64_t W = (ps.m + 63) / 64;
+                words[C.ln_pair[li]] += std::min<uint64_t>(C.wpl, W - C.ln_word0[li]);
+            }
+    for (size_t k = 0; k < np; ++k)
+        if (pairs[k].m && pairs[k].n && words[k] != (pairs[k].m + 63) / 64) return "word coverage";
+    // idle lanes read their class's all-sentinel region, long enough for
+    // every item of the class
+    std::vector<const Segment *> sent;
+    for (const Segment &sg : p.segs)
+        if (sg.pair == kNoPair) sent.push_back(&sg);
+    for (size_t ci = 0; ci < p.classes.size(); ++ci) {
+        const ClassPlan &C = p.classes[ci];
+        for (size_t li = 0; li < C.ln_pair.size(); ++li) {
+            if (C.ln_pair[li] >= 0) continue;
+            bool ok = false;
+            for (const Segment *sg : sent)
+                if (sg->begin == C.ln_ys[li] && sg->len >= C.it_T[li / kLanes] + kChunk &&
+                    C.ln_skew[li] == 0 && sg->shift == 9 + __builtin_ctz((unsigned)C.wpl))
+                    ok = true;
+            if (!ok) return "idle lane without a sentinel region";
+        }
+    }
+    // regions do not overlap
+    std::vector<std::pair<uint64_t, uint64_t>> iv;
+    for (const Segment &sg : p.segs) iv.push_back({sg.begin, sg.begin + sg.len});
+    std::sort(iv.begin(), iv.end());
+    for (size_t k = 1; k < iv.size(); ++k)
+        if (iv[k].first < iv[k - 1].second) return "stream regions overlap";
+    if (!iv.empty() && iv.back().second > p.ys_elems) return "stream region beyond the stream";
+    return std::string();
+}
+
+}  // namespace lcs

@@ -1,0 +1,112 @@
+// plan.hpp -- host-side packing of LCS pairs into wave-sized work items.
+//
+// The fill computes, for each pair, the bit-vector form of the columns of
+// the c table of section I.C: bit (i-1) of V_j is 1 exactly when
+// c[i][j] == c[i-1][j] (the column does not step up at row i).  A pair with
+// m rows needs W = ceil(m/64) 64-bit words per column.  A lane holds `wpl`
+// consecutive words of one pair, so a pair needs s = ceil(W/wpl) lanes; the
+// lanes of one pair form a "segment".
+//
+// Work item = one wavefront of 64 lanes.  Items are processed by persistent
+// waves that take them from a queue in order.  A segment of at most 64 lanes
+// lives inside one item (several segments share an item); a longer segment
+// starts at lane 0 of a fresh item and continues through consecutive items
+// (a "chain"), its carry bits handed from item to item through global
+// memory.
+//
+// Diagonal skew: lane k of a segment processes column (t - skew_k) at step t,
+// so the carry out of lane k-1 for column j is ready one step before lane k
+// needs it.  Inside an item skew grows by 1 per lane; across an item boundary
+// it grows by 1 + CHUNK, so the hand-over crosses exactly one chunk.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace lcs {
+
+constexpr int kLanes = 64;        // lanes per work item (one wavefront)
+constexpr int kChunk = 64;        // steps per chunk (carry hand-over unit)
+constexpr int kCbitsPer = 32;     // steps per stored carry-in word (uint32)
+
+struct PairShape {
+    uint64_t m = 0;   // rows (|X|)
+    uint64_t n = 0;   // columns (|Y|)
+};
+
+struct PlanConfig {
+    int wpl = 4;            // words per lane (1, 2, 4, 8)
+    bool traceback = false;
+    int ckpt = 128;         // steps between stored V checkpoints (multiple of kChunk)
+    int sigma = 4;          // alphabet size; code sigma is the zero-mask sentinel
+    bool plain = false;     // one pair per item, no packing
+};
+
+// One class = one fill launch with a fixed words-per-lane.
+struct ClassPlan {
+    int wpl = 1;
+    // items
+    std::vector<uint32_t> it_T;       // steps, multiple of kChunk
+    std::vector<int32_t> it_prev;     // item feeding lane 0 through memory, or -1
+    std::vector<uint8_t> it_feeds;    // 1 if lane 63 continues into the next item
+    std::vector<uint64_t> it_ck;      // checkpoint base (uint64 units)
+    std::vector<uint64_t> it_cb;      // carry-bit base (uint32 units)
+    std::vector<uint64_t> it_xf;      // carry hand-over base (uint64 units), for feeders
+    // lanes (item-major, kLanes per item)
+    std::vector<int32_t> ln_pair;     // -1 = idle
+    std::vector<uint32_t> ln_word0;   // first word of the pair held by the lane
+    std::vector<uint32_t> ln_skew;
+    std::vector<uint64_t> ln_ys;      // Y-stream element of column 0 of the lane's segment
+    uint64_t max_T = 0;
+    // traceback work list for this class (sorted by cost, largest first)
+    std::vector<uint32_t> tb_pair;
+    std::vector<uint32_t> tb_item;    // item holding the segment's first lane
+    std::vector<uint32_t> tb_lane0;   // lane of that item
+    uint64_t ck_words = 0, cb_words = 0, xf_words = 0;
+    uint64_t lane_steps = 0;
+};
+
+// One region of the Y stream: the pair's Y codes at columns 0..n-1 and the
+// sentinel code elsewhere, each element scaled to a byte offset into the
+// class's match-mask block (code << shift).  A region with pair == kNoPair
+// is all sentinel; idle lanes of the class read it.
+constexpr uint32_t kNoPair = 0xffffffffu;
+struct Segment {
+    uint32_t pair;
+    uint64_t begin;     // first element of the region
+    uint32_t pre;       // sentinel elements before column 0
+    uint64_t len;       // region length in elements
+    uint8_t shift;      // log2(words_per_lane * 512)
+};
+
+struct Plan {
+    PlanConfig cfg;
+    std::vector<ClassPlan> classes;
+    std::vector<Segment> segs;
+    uint64_t ys_elems = 0;        // total Y-stream elements (uint16)
+    uint64_t cells = 0;
+    uint64_t items = 0;
+    uint64_t lanes = 0;
+    uint64_t lane_steps = 0;
+    uint64_t max_T = 0;
+    std::vector<uint32_t> pair_class;   // class of each pair (UINT32_MAX if empty)
+};
+
+// Largest number of rows a pair may have for a given words-per-lane
+// (a segment may span at most kMaxChain items).
+constexpr int kMaxChain = 4096;
+inline uint64_t max_rows(int wpl) { return (uint64_t)kMaxChain * kLanes * wpl * 64; }
+
+// Largest words-per-lane the kernels accept for an alphabet size, and
+// whether a given one fits (stream element width and LDS size).
+int max_wpl(int sigma);
+bool wpl_fits(int sigma, int wpl);
+
+// Build a plan.  Returns an empty string on success, else a reason.
+std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cfg, Plan &out);
+
+// Structural checks of a plan (used by tests through the C ABI).
+std::string check_plan(const std::vector<PairShape> &pairs, const Plan &p);
+
+}  // namespace lcs

@@ -1,0 +1,370 @@
+"""Thin ctypes binding of ``liblcs_hip.so`` (C ABI in ``include/lcs.h``).
+
+Argument marshalling only: every step of the LCS computation runs in the
+library's gfx950 kernels.  The library must have been built
+(``python -m paper_1306_4627_amd.build`` or ``__graft_entry__.build()``);
+importing this module without it raises ``ImportError`` -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblcs_hip.so")
+
+LCS_OK = 0
+LCS_ERR_ARG = -1
+LCS_ERR_SYMBOL = -2
+LCS_ERR_NOMEM = -3
+LCS_ERR_DEVICE = -4
+LCS_ERR_BUFFER = -5
+LCS_ERR_TOO_LONG = -6
+LCS_ERR_UNSUPPORTED = -7
+
+LCS_WANT_TRACEBACK = 1
+LCS_USE_GRAPH = 2
+
+DNA = b"ACGT"
+PROTEIN = b"ACDEFGHIKLMNPQRSTVWY"
+
+
+class LcsError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} ({status})" if what else status_str(status))
+
+
+class lcs_alphabet(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint16), ("symbols", ctypes.POINTER(ctypes.c_uint8))]
+
+
+class lcs_pair(ctypes.Structure):
+    _fields_ = [("x", ctypes.POINTER(ctypes.c_uint8)), ("m", ctypes.c_uint64),
+                ("y", ctypes.POINTER(ctypes.c_uint8)), ("n", ctypes.c_uint64)]
+
+
+class lcs_tuning(ctypes.Structure):
+    _fields_ = [("words_per_lane", ctypes.c_int32), ("ckpt_interval", ctypes.c_int32),
+                ("persistent_waves", ctypes.c_int32), ("plain", ctypes.c_int32)]
+
+
+class lcs_batch_stats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_uint64), ("cells", ctypes.c_uint64),
+                ("groups", ctypes.c_uint64), ("lanes", ctypes.c_uint64),
+                ("lane_steps", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
+                ("words_per_lane", ctypes.c_int32), ("ckpt_interval", ctypes.c_int32),
+                ("classes", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_1306_4627_amd/build.py "
+                          "(no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    u8p, u64p, vp = P(ctypes.c_uint8), P(ctypes.c_uint64), ctypes.c_void_p
+    u64, i32 = ctypes.c_uint64, ctypes.c_int
+    lib.lcs_status_str.argtypes = [i32]
+    lib.lcs_status_str.restype = ctypes.c_char_p
+    lib.lcs_version.argtypes = []
+    lib.lcs_version.restype = ctypes.c_char_p
+    lib.lcs_create.argtypes = [P(vp), i32, ctypes.c_size_t]
+    lib.lcs_create.restype = i32
+    lib.lcs_destroy.argtypes = [vp]
+    lib.lcs_destroy.restype = None
+    lib.lcs_set_stream.argtypes = [vp, vp]
+    lib.lcs_set_stream.restype = i32
+    lib.lcs_synchronize.argtypes = [vp]
+    lib.lcs_synchronize.restype = i32
+    lib.lcs_length.argtypes = [vp, u8p, u64, u8p, u64, P(lcs_alphabet), u64p]
+    lib.lcs_length.restype = i32
+    lib.lcs_traceback.argtypes = [vp, u8p, u64, u8p, u64, P(lcs_alphabet), u8p, u64, u64p]
+    lib.lcs_traceback.restype = i32
+    lib.lcs_length_batch.argtypes = [vp, P(lcs_pair), u64, P(lcs_alphabet), u64p]
+    lib.lcs_length_batch.restype = i32
+    lib.lcs_traceback_batch.argtypes = [vp, P(lcs_pair), u64, P(lcs_alphabet), u8p, u64,
+                                        u64p, u64p]
+    lib.lcs_traceback_batch.restype = i32
+    lib.lcs_batch_create.argtypes = [vp, P(lcs_pair), u64, P(lcs_alphabet), ctypes.c_uint32,
+                                     P(lcs_tuning), P(vp)]
+    lib.lcs_batch_create.restype = i32
+    lib.lcs_batch_run.argtypes = [vp]
+    lib.lcs_batch_run.restype = i32
+    lib.lcs_batch_lengths.argtypes = [vp, u64p]
+    lib.lcs_batch_lengths.restype = i32
+    lib.lcs_batch_tracebacks.argtypes = [vp, u8p, u64, u64p, u64p]
+    lib.lcs_batch_tracebacks.restype = i32
+    lib.lcs_batch_info.argtypes = [vp, P(lcs_batch_stats)]
+    lib.lcs_batch_info.restype = i32
+    lib.lcs_batch_time.argtypes = [vp, P(ctypes.c_float), P(ctypes.c_float)]
+    lib.lcs_batch_time.restype = i32
+    lib.lcs_batch_destroy.argtypes = [vp]
+    lib.lcs_batch_destroy.restype = None
+    lib.lcs_plan_describe.argtypes = [u64p, u64p, u64, ctypes.c_uint16, ctypes.c_uint32,
+                                      P(lcs_tuning), P(lcs_batch_stats)]
+    lib.lcs_plan_describe.restype = i32
+    lib.lcs_plan_selfcheck.argtypes = [u64p, u64p, u64, ctypes.c_uint16, ctypes.c_uint32,
+                                       P(lcs_tuning)]
+    lib.lcs_plan_selfcheck.restype = i32
+    return lib
+
+
+_lib = _load()
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def status_str(status: int) -> str:
+    return _lib.lcs_status_str(int(status)).decode()
+
+
+def version() -> str:
+    return _lib.lcs_version().decode()
+
+
+def _check(status: int, what: str) -> None:
+    if status != LCS_OK:
+        raise LcsError(status, what)
+
+
+def _as_u8(s) -> np.ndarray:
+    if isinstance(s, (bytes, bytearray, memoryview)):
+        return np.frombuffer(bytes(s), dtype=np.uint8)
+    return np.ascontiguousarray(np.asarray(s, dtype=np.uint8))
+
+
+def _u8p(a: np.ndarray):
+    if a.size == 0:
+        return ctypes.POINTER(ctypes.c_uint8)()
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+class Alphabet:
+    """An alphabet (``bytes`` of distinct symbols, or None for all 256 bytes)."""
+
+    def __init__(self, symbols: Optional[bytes]):
+        if symbols is None:
+            self._buf = None
+            self.c = lcs_alphabet(256, ctypes.POINTER(ctypes.c_uint8)())
+        else:
+            self._buf = np.frombuffer(bytes(symbols), dtype=np.uint8).copy()
+            self.c = lcs_alphabet(len(symbols), _u8p(self._buf))
+
+    @property
+    def size(self) -> int:
+        return int(self.c.size)
+
+
+def _alpha(a) -> Alphabet:
+    if isinstance(a, Alphabet):
+        return a
+    if a is None or a == "byte":
+        return Alphabet(None)
+    if isinstance(a, str):
+        return Alphabet({"dna": DNA, "protein": PROTEIN}[a])
+    return Alphabet(bytes(a))
+
+
+def _tuning(words_per_lane=0, ckpt_interval=0, persistent_waves=0, plain=False):
+    return lcs_tuning(int(words_per_lane), int(ckpt_interval), int(persistent_waves), int(bool(plain)))
+
+
+class _Pairs:
+    """Keeps the numpy buffers alive while the C array points into them."""
+
+    def __init__(self, pairs: Sequence[Tuple[object, object]]):
+        self.bufs = []
+        self.arr = (lcs_pair * max(1, len(pairs)))()
+        self.count = len(pairs)
+        for k, (x, y) in enumerate(pairs):
+            xa, ya = _as_u8(x), _as_u8(y)
+            self.bufs += [xa, ya]
+            self.arr[k] = lcs_pair(_u8p(xa), xa.size, _u8p(ya), ya.size)
+
+    def ptr(self):
+        return self.arr if self.count else ctypes.POINTER(lcs_pair)()
+
+
+class Context:
+    """One device, one stream, a device-memory budget (``lcs_create``)."""
+
+    def __init__(self, device: int = 0, mem_budget_bytes: int = 0):
+        h = ctypes.c_void_p()
+        _check(_lib.lcs_create(ctypes.byref(h), int(device), int(mem_budget_bytes)), "lcs_create")
+        self.h = h
+
+    def close(self) -> None:
+        if self.h:
+            _lib.lcs_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream) -> None:
+        """Use a HIP stream: an int handle, a ``torch.cuda.Stream`` or None."""
+        handle = None
+        if stream is not None:
+            handle = getattr(stream, "cuda_stream", stream)
+        _check(_lib.lcs_set_stream(self.h, ctypes.c_void_p(handle) if handle else None),
+               "lcs_set_stream")
+
+    def synchronize(self) -> None:
+        _check(_lib.lcs_synchronize(self.h), "lcs_synchronize")
+
+
+def lcs_length(ctx: Context, x, y, alphabet="dna") -> int:
+    xa, ya = _as_u8(x), _as_u8(y)
+    al = _alpha(alphabet)
+    out = ctypes.c_uint64()
+    _check(_lib.lcs_length(ctx.h, _u8p(xa), xa.size, _u8p(ya), ya.size, ctypes.byref(al.c),
+                           ctypes.byref(out)), "lcs_length")
+    return int(out.value)
+
+
+def lcs_traceback(ctx: Context, x, y, alphabet="dna") -> bytes:
+    xa, ya = _as_u8(x), _as_u8(y)
+    al = _alpha(alphabet)
+    cap = min(xa.size, ya.size)
+    buf = np.zeros(max(1, cap), dtype=np.uint8)
+    out = ctypes.c_uint64()
+    _check(_lib.lcs_traceback(ctx.h, _u8p(xa), xa.size, _u8p(ya), ya.size, ctypes.byref(al.c),
+                              _u8p(buf), cap, ctypes.byref(out)), "lcs_traceback")
+    return buf[:out.value].tobytes()
+
+
+def lcs_length_batch(ctx: Context, pairs, alphabet="dna") -> np.ndarray:
+    pp = _Pairs(pairs)
+    al = _alpha(alphabet)
+    out = np.zeros(max(1, pp.count), dtype=np.uint64)
+    _check(_lib.lcs_length_batch(ctx.h, pp.ptr(), pp.count, ctypes.byref(al.c),
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))),
+           "lcs_length_batch")
+    return out[:pp.count]
+
+
+def lcs_traceback_batch(ctx: Context, pairs, alphabet="dna") -> List[bytes]:
+    pp = _Pairs(pairs)
+    al = _alpha(alphabet)
+    cap = sum(min(len(_as_u8(x)), len(_as_u8(y))) for x, y in pairs)
+    arena = np.zeros(max(1, cap), dtype=np.uint8)
+    offs = np.zeros(max(1, pp.count), dtype=np.uint64)
+    lens = np.zeros(max(1, pp.count), dtype=np.uint64)
+    P64 = ctypes.POINTER(ctypes.c_uint64)
+    _check(_lib.lcs_traceback_batch(ctx.h, pp.ptr(), pp.count, ctypes.byref(al.c), _u8p(arena),
+                                    cap, offs.ctypes.data_as(P64), lens.ctypes.data_as(P64)),
+           "lcs_traceback_batch")
+    return [arena[int(o):int(o) + int(l)].tobytes() for o, l in zip(offs[:pp.count], lens[:pp.count])]
+
+
+class Batch:
+    """A resident batch (``lcs_batch_create``): inputs uploaded once, run many times."""
+
+    def __init__(self, ctx: Context, pairs, alphabet="dna", traceback: bool = False,
+                 graph: bool = False, words_per_lane: int = 0, ckpt_interval: int = 0,
+                 persistent_waves: int = 0, plain: bool = False):
+        self.ctx = ctx
+        self._pairs = _Pairs(pairs)
+        self.count = self._pairs.count
+        self._alpha = _alpha(alphabet)
+        self.traceback = traceback
+        self.cap = sum(min(len(_as_u8(x)), len(_as_u8(y))) for x, y in pairs)
+        flags = (LCS_WANT_TRACEBACK if traceback else 0) | (LCS_USE_GRAPH if graph else 0)
+        t = _tuning(words_per_lane, ckpt_interval, persistent_waves, plain)
+        h = ctypes.c_void_p()
+        _check(_lib.lcs_batch_create(ctx.h, self._pairs.ptr(), self.count,
+                                     ctypes.byref(self._alpha.c), flags, ctypes.byref(t),
+                                     ctypes.byref(h)), "lcs_batch_create")
+        self.h = h
+        # inputs are on the device now; host copies are no longer needed
+        self._pairs = None
+
+    def run(self) -> None:
+        _check(_lib.lcs_batch_run(self.h), "lcs_batch_run")
+
+    def lengths(self) -> np.ndarray:
+        out = np.zeros(max(1, self.count), dtype=np.uint64)
+        _check(_lib.lcs_batch_lengths(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))),
+               "lcs_batch_lengths")
+        return out[:self.count]
+
+    def tracebacks(self) -> List[bytes]:
+        arena = np.zeros(max(1, self.cap), dtype=np.uint8)
+        offs = np.zeros(max(1, self.count), dtype=np.uint64)
+        lens = np.zeros(max(1, self.count), dtype=np.uint64)
+        P64 = ctypes.POINTER(ctypes.c_uint64)
+        _check(_lib.lcs_batch_tracebacks(self.h, _u8p(arena), self.cap, offs.ctypes.data_as(P64),
+                                         lens.ctypes.data_as(P64)), "lcs_batch_tracebacks")
+        return [arena[int(o):int(o) + int(l)].tobytes()
+                for o, l in zip(offs[:self.count], lens[:self.count])]
+
+    def info(self) -> dict:
+        s = lcs_batch_stats()
+        _check(_lib.lcs_batch_info(self.h, ctypes.byref(s)), "lcs_batch_info")
+        return s.as_dict()
+
+    def time(self) -> Tuple[float, float]:
+        """(total_ms, fill_ms) of one run, from HIP events on the batch's stream."""
+        t, f = ctypes.c_float(), ctypes.c_float()
+        _check(_lib.lcs_batch_time(self.h, ctypes.byref(t), ctypes.byref(f)), "lcs_batch_time")
+        return float(t.value), float(f.value)
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            _lib.lcs_batch_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_describe(m, n, alphabet_size: int = 4, traceback: bool = False, **tuning) -> dict:
+    """Host-only: how a batch of these shapes would be packed (no device)."""
+    ma = np.ascontiguousarray(np.asarray(m, dtype=np.uint64))
+    na = np.ascontiguousarray(np.asarray(n, dtype=np.uint64))
+    s = lcs_batch_stats()
+    t = _tuning(**tuning)
+    P64 = ctypes.POINTER(ctypes.c_uint64)
+    _check(_lib.lcs_plan_describe(ma.ctypes.data_as(P64), na.ctypes.data_as(P64), ma.size,
+                                  alphabet_size, LCS_WANT_TRACEBACK if traceback else 0,
+                                  ctypes.byref(t), ctypes.byref(s)), "lcs_plan_describe")
+    return s.as_dict()
+
+
+def plan_selfcheck(m, n, alphabet_size: int = 4, traceback: bool = False, **tuning) -> int:
+    """Host-only structural check of the packer; returns the status code."""
+    ma = np.ascontiguousarray(np.asarray(m, dtype=np.uint64))
+    na = np.ascontiguousarray(np.asarray(n, dtype=np.uint64))
+    t = _tuning(**tuning)
+    P64 = ctypes.POINTER(ctypes.c_uint64)
+    return int(_lib.lcs_plan_selfcheck(ma.ctypes.data_as(P64), na.ctypes.data_as(P64), ma.size,
+                                       alphabet_size, LCS_WANT_TRACEBACK if traceback else 0,
+                                       ctypes.byref(t)))

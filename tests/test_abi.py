@@ -1,0 +1,133 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function the
+header declares, validates arguments before touching a device, and packs
+pairs correctly (host-only planner).  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1306_4627_amd import inputs, lcs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lcs.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lcs_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_are_exported():
+    names = _declared_functions()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lcs.lib(), name), f"{name} declared in lcs.h but not exported"
+
+
+def test_status_strings_and_version():
+    assert lcs.status_str(0) == "ok"
+    for code in range(-7, 0):
+        assert lcs.status_str(code) and lcs.status_str(code) != "unknown status"
+    assert lcs.status_str(-99) == "unknown status"
+    assert "gfx950" in lcs.version()
+
+
+def _no_gpu():
+    try:
+        import torch
+        return not torch.cuda.is_available()
+    except Exception:
+        return True
+
+
+@pytest.mark.skipif(not _no_gpu(), reason="checks the no-device path")
+def test_create_without_device_fails_cleanly():
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.Context(0)
+    assert e.value.status == lcs.LCS_ERR_DEVICE
+
+
+def test_null_arguments_rejected_before_any_device_call():
+    L = lcs.lib()
+    out = ctypes.c_uint64(7)
+    al = lcs.lcs_alphabet(4, ctypes.cast(ctypes.c_char_p(b"ACGT"), ctypes.POINTER(ctypes.c_uint8)))
+    assert L.lcs_length(None, None, 0, None, 0, ctypes.byref(al), ctypes.byref(out)) == lcs.LCS_ERR_ARG
+    assert out.value == 7   # untouched on error
+    assert L.lcs_create(None, 0, 0) == lcs.LCS_ERR_ARG
+    assert L.lcs_set_stream(None, None) == lcs.LCS_ERR_ARG
+    assert L.lcs_synchronize(None) == lcs.LCS_ERR_ARG
+    assert L.lcs_batch_run(None) == lcs.LCS_ERR_ARG
+    assert L.lcs_batch_info(None, None) == lcs.LCS_ERR_ARG
+    L.lcs_destroy(None)
+    L.lcs_batch_destroy(None)
+
+
+def test_plan_rejects_bad_tuning_and_alphabets():
+    m, n = [100, 200], [300, 50]
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.plan_describe(m, n, 4, words_per_lane=3)
+    assert e.value.status == lcs.LCS_ERR_ARG
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.plan_describe(m, n, 4, traceback=True, ckpt_interval=100)
+    assert e.value.status == lcs.LCS_ERR_ARG
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.plan_describe(m, n, 200)
+    assert e.value.status == lcs.LCS_ERR_UNSUPPORTED
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.plan_describe(m, n, 20, words_per_lane=8)
+    assert e.value.status == lcs.LCS_ERR_UNSUPPORTED
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.plan_describe([1 << 40], [5], 4)
+    assert e.value.status == lcs.LCS_ERR_TOO_LONG
+
+
+@pytest.mark.parametrize("wpl", [0, 1, 2, 4, 8])
+@pytest.mark.parametrize("tb", [False, True])
+def test_packer_edge_lengths(wpl, tb):
+    lens = [0, 1, 2, 63, 64, 65, 127, 128, 129, 4095, 4096, 4097, 16384, 16385, 70000]
+    m = [a for a in lens for _ in lens]
+    n = [b for _ in lens for b in lens]
+    assert lcs.plan_selfcheck(m, n, 4, traceback=tb, words_per_lane=wpl) == 0
+    d = lcs.plan_describe(m, n, 4, traceback=tb, words_per_lane=wpl)
+    assert d["cells"] == sum(a * b for a, b in zip(m, n))
+    assert d["pairs"] == len(m)
+
+
+def test_packer_plain_mode_one_pair_per_item():
+    g = np.random.default_rng(0)
+    m = g.integers(1, 3000, size=200)
+    n = g.integers(1, 3000, size=200)
+    assert lcs.plan_selfcheck(m, n, 4, plain=True) == 0
+    d = lcs.plan_describe(m, n, 4, plain=True, words_per_lane=1)
+    # every pair of at most 64 lanes owns a whole item
+    assert d["groups"] >= 200
+
+
+def test_packer_short_batch_full_size():
+    ps = inputs.batch_short(65536)
+    m = [p.x.size for p in ps]
+    n = [p.y.size for p in ps]
+    for w in (0, 1, 2):
+        assert lcs.plan_selfcheck(m, n, 20, words_per_lane=w) == 0
+    d = lcs.plan_describe(m, n, 20)
+    useful = sum(a * b for a, b in zip(m, n))
+    # lane-steps hold 64 cells each; packing keeps most of them busy
+    assert useful / (d["lane_steps"] * 64) > 0.7
+
+
+def test_packer_related_batch_full_size():
+    rng = np.random.Generator(np.random.PCG64(inputs.BASE_SEED + 41))
+    lx = np.floor(np.exp(rng.uniform(np.log(256), np.log(65536), size=4096))).astype(np.int64)
+    ly = (lx * rng.uniform(0.9, 1.1, size=4096)).astype(np.int64)
+    for w in (0, 1, 4, 8):
+        assert lcs.plan_selfcheck(lx, ly, 4, traceback=True, words_per_lane=w) == 0
+
+
+def test_packer_long_pair_chains():
+    for w in (1, 2, 4, 8):
+        assert lcs.plan_selfcheck([262144], [262144 + 77], 4, traceback=True, words_per_lane=w) == 0
+        d = lcs.plan_describe([262144], [262144], 4, words_per_lane=w)
+        assert d["groups"] == -(-262144 // (64 * 64 * w))

@@ -1,0 +1,303 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+element by element, bit-exact for lengths and traceback strings.
+
+Every case prints its name before it touches the GPU so that a failing run
+names it.
+"""
+import os
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1306_4627_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lcs():
+    from paper_1306_4627_amd import lcs as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(lcs):
+    c = lcs.Context(0)
+    yield c
+    c.close()
+
+
+def _oracle_lengths(pairs):
+    with ThreadPoolExecutor(THREADS) as ex:
+        return np.array(list(ex.map(lambda p: oracle.lcs_length(p[0], p[1]), pairs)), dtype=np.uint64)
+
+
+def _oracle_tracebacks(pairs, ckpt_rows=None):
+    def one(p):
+        x, y = p
+        if ckpt_rows or (len(x) + 1) * (len(y) + 1) > 3e8:
+            return oracle.lcs_traceback_ckpt(x, y, ckpt_rows or 512)
+        return oracle.lcs_traceback(x, y)
+    with ThreadPoolExecutor(THREADS) as ex:
+        return list(ex.map(one, pairs))
+
+
+def _rand(g, n, al):
+    return inputs.random_seq(g, n, al)
+
+
+EDGE = [0, 1, 2, 3, 31, 32, 33, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 1000, 1023, 1024, 1025]
+
+
+@pytest.mark.parametrize("alname", ["dna", "protein", "AB", "A"])
+def test_single_pairs_edge_lengths(ctx, lcs, alname):
+    al = {"dna": inputs.DNA, "protein": inputs.PROTEIN, "AB": b"AB", "A": b"A"}[alname]
+    g = inputs.rng(5000 + len(al))
+    lens = [0, 1, 2, 63, 64, 65, 128, 129, 700]
+    for m in lens:
+        for n in (0, 1, 64, 65, 300):
+            x, y = _rand(g, m, al), _rand(g, n, al)
+            _say(f"single {alname} m={m} n={n}")
+            assert lcs.lcs_length(ctx, x, y, al) == oracle.lcs_length(x, y), (m, n)
+            assert lcs.lcs_traceback(ctx, x, y, al) == oracle.lcs_traceback(x, y), (m, n)
+
+
+@pytest.mark.parametrize("wpl", [1, 2, 4, 8])
+def test_batch_edge_lengths_lengths_and_tracebacks(ctx, lcs, wpl):
+    g = inputs.rng(6000 + wpl)
+    pairs = []
+    for m in EDGE:
+        for n in (0, 1, 5, 64, 65, 333, 1025):
+            pairs.append((_rand(g, m, inputs.DNA), _rand(g, n, inputs.DNA)))
+    _say(f"batch edge wpl={wpl} pairs={len(pairs)}")
+    with lcs.Batch(ctx, pairs, "dna", traceback=True, words_per_lane=wpl) as b:
+        b.run()
+        got_L = b.lengths()
+        got_S = b.tracebacks()
+    assert np.array_equal(got_L, _oracle_lengths(pairs))
+    want_S = _oracle_tracebacks(pairs)
+    for k, (a, w) in enumerate(zip(got_S, want_S)):
+        assert a == w, f"pair {k}: m={len(pairs[k][0])} n={len(pairs[k][1])}"
+
+
+@pytest.mark.parametrize("ckpt", [64, 128, 256])
+def test_traceback_checkpoint_intervals(ctx, lcs, ckpt):
+    g = inputs.rng(6100 + ckpt)
+    pairs = []
+    for _ in range(30):
+        m = int(g.integers(1, 3000))
+        x = _rand(g, m, inputs.DNA)
+        y, _ = inputs.mutate(g, x, float(g.uniform(0.05, 0.4)), inputs.DNA)
+        pairs.append((x, y))
+    _say(f"ckpt={ckpt}")
+    with lcs.Batch(ctx, pairs, "dna", traceback=True, ckpt_interval=ckpt) as b:
+        b.run()
+        assert b.tracebacks() == _oracle_tracebacks(pairs)
+
+
+@pytest.mark.parametrize("wpl", [1, 2, 4])
+def test_chained_items_long_rows(ctx, lcs, wpl):
+    # rows beyond one wave (64 lanes * wpl words * 64 bits) chain several
+    # work items through memory
+    g = inputs.rng(6200 + wpl)
+    pairs = []
+    for m in (4095, 4096, 4097, 8192 + 1, 64 * 64 * wpl * 2 + 65, 20000):
+        x = _rand(g, m, inputs.DNA)
+        y, _ = inputs.mutate(g, x, 0.2, inputs.DNA)
+        pairs.append((x, y))
+        pairs.append((_rand(g, m, inputs.DNA), _rand(g, int(g.integers(1, 5000)), inputs.DNA)))
+    _say(f"chains wpl={wpl}")
+    with lcs.Batch(ctx, pairs, "dna", traceback=True, words_per_lane=wpl) as b:
+        b.run()
+        L = b.lengths()
+        S = b.tracebacks()
+    assert np.array_equal(L, _oracle_lengths(pairs))
+    assert S == _oracle_tracebacks(pairs)
+
+
+def test_adversarial_inputs(ctx, lcs):
+    g = inputs.rng(6300)
+    x = _rand(g, 5000, inputs.DNA)
+    cases = {
+        "x_eq_y": (x, x.copy()),
+        "all_same": (np.full(3000, ord("A"), np.uint8), np.full(2000, ord("A"), np.uint8)),
+        "disjoint": (np.full(3000, ord("A"), np.uint8), np.full(2500, ord("C"), np.uint8)),
+        "periodic": (np.frombuffer(b"ACGT" * 1000, np.uint8), np.frombuffer(b"CGTA" * 900, np.uint8)),
+        "ripple": (np.full(4100, ord("A"), np.uint8), np.frombuffer(b"A" + b"C" * 3000 + b"A" * 50, np.uint8)),
+        "subseq": (x[::3].copy(), x),
+        "one_row": (x[:1], x),
+        "one_col": (x, x[:1]),
+    }
+    pairs = list(cases.values())
+    _say("adversarial batch")
+    for wpl in (1, 4):
+        with lcs.Batch(ctx, pairs, "dna", traceback=True, words_per_lane=wpl) as b:
+            b.run()
+            L = b.lengths()
+            S = b.tracebacks()
+        for (name, (a, c)), l, s in zip(cases.items(), L, S):
+            assert l == oracle.lcs_length(a, c), name
+            assert s == oracle.lcs_traceback(a, c), name
+    assert S[0] == x.tobytes()
+
+
+def test_batch_order_and_plain_agree(ctx, lcs):
+    g = inputs.rng(6400)
+    pairs = []
+    for _ in range(300):
+        m, n = int(g.integers(0, 2500)), int(g.integers(0, 2500))
+        pairs.append((_rand(g, m, inputs.PROTEIN), _rand(g, n, inputs.PROTEIN)))
+    _say("order/plain")
+    with lcs.Batch(ctx, pairs, "protein", traceback=True) as b:
+        b.run()
+        L1, S1 = b.lengths(), b.tracebacks()
+    perm = g.permutation(len(pairs))
+    with lcs.Batch(ctx, [pairs[k] for k in perm], "protein", traceback=True) as b:
+        b.run()
+        L2, S2 = b.lengths(), b.tracebacks()
+    with lcs.Batch(ctx, pairs[:60], "protein", traceback=True, plain=True) as b:
+        b.run()
+        L3, S3 = b.lengths(), b.tracebacks()
+    assert np.array_equal(L1, _oracle_lengths(pairs))
+    assert np.array_equal(L2, L1[perm])
+    assert [S2[k] for k in range(len(perm))] == [S1[k] for k in perm]
+    assert np.array_equal(L3, L1[:60]) and S3 == S1[:60]
+    assert S1 == _oracle_tracebacks(pairs)
+
+
+def test_graph_replays_match_eager(ctx, lcs):
+    g = inputs.rng(6500)
+    pairs = [(_rand(g, int(a), inputs.DNA), _rand(g, int(c), inputs.DNA))
+             for a, c in g.integers(1, 6000, size=(50, 2))]
+    want_L = _oracle_lengths(pairs)
+    want_S = _oracle_tracebacks(pairs)
+    _say("graph replays")
+    with lcs.Batch(ctx, pairs, "dna", traceback=True, graph=True) as b:
+        for rep in range(4):
+            b.run()
+            assert np.array_equal(b.lengths(), want_L), rep
+            assert b.tracebacks() == want_S, rep
+            # eager work between replays
+            assert lcs.lcs_length(ctx, pairs[rep][0], pairs[rep][1], "dna") == want_L[rep]
+
+
+def test_one_call_batch_entry_points(ctx, lcs):
+    g = inputs.rng(6600)
+    pairs = [(_rand(g, int(a), inputs.PROTEIN), _rand(g, int(c), inputs.PROTEIN))
+             for a, c in g.integers(0, 900, size=(100, 2))]
+    _say("one-call batch")
+    L = lcs.lcs_length_batch(ctx, pairs, "protein")
+    S = lcs.lcs_traceback_batch(ctx, pairs, "protein")
+    assert np.array_equal(L, _oracle_lengths(pairs))
+    assert S == _oracle_tracebacks(pairs)
+
+
+def test_bit_vector_identity_through_prefixes(ctx, lcs):
+    # c[i][n] for every prefix X_i equals the LCS length of (X_i, Y): the
+    # batch of all prefixes pins every bit of the final column vector
+    g = inputs.rng(6700)
+    x = _rand(g, 300, inputs.DNA)
+    y = _rand(g, 280, inputs.DNA)
+    pairs = [(x[:i], y) for i in range(0, 301)]
+    _say("prefix column")
+    got = lcs.lcs_length_batch(ctx, pairs, "dna")
+    c, _ = oracle.lcs_tables(x, y)
+    assert np.array_equal(got, c[:, -1].astype(np.uint64))
+
+
+def test_error_paths_leave_outputs_untouched(ctx, lcs):
+    _say("error paths")
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.lcs_length(ctx, b"ACGX", b"ACG", "dna")
+    assert e.value.status == lcs.LCS_ERR_SYMBOL
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.Batch(ctx, [(b"AC", b"CA")], "dna", words_per_lane=3)
+    assert e.value.status == lcs.LCS_ERR_ARG
+    small = lcs.Context(0, mem_budget_bytes=4096)
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.Batch(small, [(b"ACGT" * 100, b"TGCA" * 100)], "dna")
+    assert e.value.status == lcs.LCS_ERR_NOMEM
+    small.close()
+
+
+# --------------------------------------------------------------------------
+# full-size workloads, in the launch configuration of the benchmark
+# --------------------------------------------------------------------------
+
+def test_full_pair_dna_4096(ctx, lcs):
+    p = inputs.pair_dna_4096()
+    _say("full 4096x4096 pair")
+    assert lcs.lcs_length(ctx, p.x, p.y, "dna") == oracle.lcs_length(p.x, p.y)
+    assert lcs.lcs_traceback(ctx, p.x, p.y, "dna") == oracle.lcs_traceback(p.x, p.y)
+
+
+def test_full_batch_short_sampled(ctx, lcs):
+    ps = inputs.batch_short()
+    pairs = [(p.x, p.y) for p in ps]
+    _say("full short batch (65536 pairs)")
+    with lcs.Batch(ctx, pairs, "protein", graph=True) as b:
+        b.run()
+        L = b.lengths()
+    g = np.random.default_rng(1)
+    idx = np.concatenate([g.choice(len(pairs), 3000, replace=False), np.arange(64)])
+    want = _oracle_lengths([pairs[k] for k in idx])
+    assert np.array_equal(L[idx], want)
+    lens = np.array([min(p.x.size, p.y.size) for p in ps])
+    assert np.all(L <= lens) and np.all(L > 0)
+
+
+def test_full_batch_related_sampled(ctx, lcs):
+    ps = inputs.batch_related()
+    pairs = [(p.x, p.y) for p in ps]
+    _say("full related batch (4096 pairs, tracebacks)")
+    with lcs.Batch(ctx, pairs, "dna", traceback=True, graph=True) as b:
+        b.run()
+        L = b.lengths()
+        S = b.tracebacks()
+    # properties on every pair
+    for p, l, s in zip(ps, L, S):
+        assert len(s) == l <= min(p.x.size, p.y.size)
+        assert l >= p.x.size - (p.log.substitutions + p.log.deletions)
+    sizes = np.array([p.cells for p in ps])
+    order = np.argsort(sizes)
+    idx = list(order[:40]) + list(order[len(order) // 2: len(order) // 2 + 8]) + list(order[-2:])
+    sub = [pairs[k] for k in idx]
+    want_L = _oracle_lengths(sub)
+    assert np.array_equal(L[idx], want_L)
+    want_S = _oracle_tracebacks(sub)
+    for k, w in zip(idx, want_S):
+        assert S[k] == w, f"pair {k}"
+    for k in range(0, len(ps), 97):   # common-subsequence check on a spread
+        assert oracle.is_subsequence(S[k], pairs[k][0].tobytes())
+        assert oracle.is_subsequence(S[k], pairs[k][1].tobytes())
+
+
+def test_full_long_related_pair(ctx, lcs):
+    p = inputs.pair_long_related()
+    _say("full long related pair 262144")
+    L = lcs.lcs_length(ctx, p.x, p.y, "dna")
+    S = lcs.lcs_traceback(ctx, p.x, p.y, "dna")
+    assert len(S) == L
+    assert L >= p.x.size - (p.log.substitutions + p.log.deletions)
+    assert L <= min(p.x.size, p.y.size)
+    assert oracle.is_subsequence(S, p.x.tobytes()) and oracle.is_subsequence(S, p.y.tobytes())
+
+
+def test_long_related_pair_scaled_exact(ctx, lcs):
+    # same recipe and launch shape (chained items) at a size the oracle
+    # finishes in seconds
+    x = inputs.random_seq(inputs.rng(21), 40000, inputs.DNA)
+    y, _ = inputs.mutate(inputs.rng(22), x, 0.10, inputs.DNA)
+    _say("long related pair 40000 exact")
+    assert lcs.lcs_length(ctx, x, y, "dna") == oracle.lcs_length(x, y)
+    assert lcs.lcs_traceback(ctx, x, y, "dna") == oracle.lcs_traceback_ckpt(x, y, 1024)
