@@ -131,7 +131,7 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
                         uint64_t pos = h * kLanes + l;
                         C.ln_pair[li] = (int32_t)k;
                         C.ln_word0[li] = (uint32_t)(pos * wpl);
-                        C.ln_skew[li] = (uint32_t)(h * (kLanes + kChunk) + l);
+                        C.ln_skew[li] = (uint32_t)(h * (kLanes - 1 + kChunk) + l);
                     }
                     item_segs[it].push_back(seg_id);
                     prev = it;
@@ -140,7 +140,7 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
                 }
                 uint64_t last_pos = s - 1;
                 uint64_t hl = last_pos / kLanes;
-                uint32_t pre = (uint32_t)(hl * (kLanes + kChunk) + (last_pos % kLanes));
+                uint32_t pre = (uint32_t)(hl * (kLanes - 1 + kChunk) + (last_pos % kLanes));
                 C.tb_pair.push_back(k);
                 C.tb_item.push_back((uint32_t)first);
                 C.tb_lane0.push_back(0);
@@ -286,7 +286,7 @@ std::string check_plan(const std::vector<PairShape> &pairs, const Plan &p) {
                         below_pair = C.ln_pair[lb];
                         below_word0 = C.ln_word0[lb];
                         below_skew = C.ln_skew[lb];
-                        if (C.ln_skew[li] != below_skew + 1 + kChunk) return "skew step across items";
+                        if (C.ln_skew[li] != below_skew + kChunk) return "skew step across items";
                     }
                     if (below_pair != pr || below_word0 + C.wpl != word0) return "segment not contiguous";
                 } else {

@@ -17,7 +17,9 @@
 // Diagonal skew: lane k of a segment processes column (t - skew_k) at step t,
 // so the carry out of lane k-1 for column j is ready one step before lane k
 // needs it.  Inside an item skew grows by 1 per lane; across an item boundary
-// it grows by 1 + CHUNK, so the hand-over crosses exactly one chunk.
+// it grows by CHUNK, so lane 0 of the next item uses, at step t, the carry
+// lane 63 of the previous item produced at step t - CHUNK: the same bit
+// position of the previous chunk's hand-over word.
 #pragma once
 
 #include <cstdint>
