@@ -117,6 +117,10 @@ const char *lcs_status_str(int status);
 /* Library version string; static storage. */
 const char *lcs_version(void);
 
+/* Text of the last HIP runtime error or kernel failure seen by this thread
+ * ("" if none); thread-local storage, valid until the next call. */
+const char *lcs_last_error(void);
+
 /* Create a context on HIP device `device`.  mem_budget_bytes caps the device
  * memory the context's batches may hold (0 = 90% of the device's free memory
  * at creation).  Returns LCS_ERR_DEVICE when the device is absent or is not a
@@ -186,11 +190,13 @@ lcs_status lcs_batch_tracebacks(lcs_batch *batch, uint8_t *out_arena, uint64_t a
 /* Describe how the batch was planned. */
 lcs_status lcs_batch_info(const lcs_batch *batch, lcs_batch_stats *out);
 
-/* Run the batch once (as lcs_batch_run does, graph or not), wait for it and
- * report its HIP-event timings (inputs already resident).  *total_ms
+/* Run the batch once, wait for it and report HIP-event timings (inputs
+ * already resident).  eager == 0 runs it as lcs_batch_run does (a graph
+ * replay if planned with LCS_USE_GRAPH); eager != 0 enqueues the kernels
+ * directly, which also times the fill kernels on their own.  *total_ms
  * receives the duration of the whole pass, *fill_ms that of the fill kernels
- * alone (-1 if they could not be timed separately); either may be NULL. */
-lcs_status lcs_batch_time(lcs_batch *batch, float *total_ms, float *fill_ms);
+ * alone, or -1 for a graph replay; either pointer may be NULL. */
+lcs_status lcs_batch_time(lcs_batch *batch, int eager, float *total_ms, float *fill_ms);
 
 /* Release a batch (NULL is ignored). */
 void lcs_batch_destroy(lcs_batch *batch);

@@ -99,7 +99,6 @@ struct lcs_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool ran = false;
-    bool graph_events = false;   // the graph records the four events itself
     bool timed_fill = false;     // the last pass recorded the fill events
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
@@ -108,6 +107,13 @@ struct lcs_batch {
 // small helpers
 // --------------------------------------------------------------------------
 
+static thread_local char g_last_error[256] = "";
+
+static void note_error(const char *what, hipError_t e) {
+    std::snprintf(g_last_error, sizeof g_last_error, "%s: %s (%d)", what, hipGetErrorString(e),
+                  (int)e);
+}
+
 static lcs_status dev_err(hipError_t e) {
     return e == hipSuccess ? LCS_OK : (e == hipErrorOutOfMemory ? LCS_ERR_NOMEM : LCS_ERR_DEVICE);
 }
@@ -115,7 +121,10 @@ static lcs_status dev_err(hipError_t e) {
 #define HIP_TRY(expr)                                  \
     do {                                               \
         hipError_t e_ = (expr);                        \
-        if (e_ != hipSuccess) return dev_err(e_);      \
+        if (e_ != hipSuccess) {                        \
+            note_error(#expr, e_);                     \
+            return dev_err(e_);                        \
+        }                                              \
     } while (0)
 
 // Build the byte -> code table: codes 0..size-1 in the order the alphabet
@@ -207,6 +216,8 @@ extern "C" const char *lcs_status_str(int s) {
 }
 
 extern "C" const char *lcs_version(void) { return LCS_VERSION_STRING; }
+
+extern "C" const char *lcs_last_error(void) { return g_last_error; }
 
 // --------------------------------------------------------------------------
 // context
@@ -666,41 +677,28 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
 // Launch one pass.  Graph batches capture the sequence once (with the HIP
 // event records as graph nodes, so per-pass timings stay readable) and replay
 // it; the others enqueue the kernels directly.
-static lcs_status launch_pass(lcs_batch *b) {
+static lcs_status launch_pass(lcs_batch *b, bool eager) {
     lcs_ctx *ctx = b->ctx;
     if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
     hipStream_t s = ctx->stream;
-    if ((b->flags & LCS_USE_GRAPH) && !b->plain) {
+    if ((b->flags & LCS_USE_GRAPH) && !b->plain && !eager) {
         if (!b->gexec) {
-            for (int attempt = 0; attempt < 2 && !b->gexec; ++attempt) {
-                const bool with_events = attempt == 0;
-                HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                lcs_status st = enqueue(b, s, with_events);
-                hipGraph_t g = nullptr;
-                hipError_t e = hipStreamEndCapture(s, &g);
-                if (st != LCS_OK || e != hipSuccess) {
-                    if (g) (void)hipGraphDestroy(g);
-                    (void)hipGetLastError();
-                    if (attempt == 1) return st != LCS_OK ? st : dev_err(e);
-                    continue;
-                }
-                hipGraphExec_t ge = nullptr;
-                e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-                if (e != hipSuccess) {
-                    (void)hipGraphDestroy(g);
-                    (void)hipGetLastError();
-                    if (attempt == 1) return dev_err(e);
-                    continue;
-                }
-                b->graph = g;
-                b->gexec = ge;
-                b->graph_events = with_events;
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            lcs_status st = enqueue(b, s, false);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(s, &g);
+            if (st != LCS_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
             }
+            HIP_TRY(e);
+            b->graph = g;
+            HIP_TRY(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
         }
-        if (!b->graph_events) HIP_TRY(hipEventRecord(b->ev[0], s));
+        HIP_TRY(hipEventRecord(b->ev[0], s));
         HIP_TRY(hipGraphLaunch(b->gexec, s));
-        if (!b->graph_events) HIP_TRY(hipEventRecord(b->ev[3], s));
-        b->timed_fill = b->graph_events;
+        HIP_TRY(hipEventRecord(b->ev[3], s));
+        b->timed_fill = false;
     } else {
         lcs_status st = enqueue(b, s, true);
         if (st) return st;
@@ -712,7 +710,7 @@ static lcs_status launch_pass(lcs_batch *b) {
 
 extern "C" lcs_status lcs_batch_run(lcs_batch *b) {
     if (!b) return LCS_ERR_ARG;
-    return launch_pass(b);
+    return launch_pass(b, false);
 }
 
 static lcs_status finish(lcs_batch *b) {
@@ -722,7 +720,11 @@ static lcs_status finish(lcs_batch *b) {
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     uint32_t err = 0;
     HIP_TRY(hipMemcpy(&err, b->error, 4, hipMemcpyDeviceToHost));
-    if (err) return LCS_ERR_DEVICE;
+    if (err) {
+        std::snprintf(g_last_error, sizeof g_last_error,
+                      "a carry hand-over wait ran out of polls (kernel error flag %u)", err);
+        return LCS_ERR_DEVICE;
+    }
     return LCS_OK;
 }
 
@@ -766,9 +768,9 @@ extern "C" lcs_status lcs_batch_info(const lcs_batch *b, lcs_batch_stats *out) {
     return LCS_OK;
 }
 
-extern "C" lcs_status lcs_batch_time(lcs_batch *b, float *total_ms, float *fill_ms) {
+extern "C" lcs_status lcs_batch_time(lcs_batch *b, int eager, float *total_ms, float *fill_ms) {
     if (!b) return LCS_ERR_ARG;
-    lcs_status st = launch_pass(b);
+    lcs_status st = launch_pass(b, eager != 0);
     if (st) return st;
     st = finish(b);
     if (st) return st;

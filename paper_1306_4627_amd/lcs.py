@@ -36,7 +36,11 @@ PROTEIN = b"ACDEFGHIKLMNPQRSTVWY"
 class LcsError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
-        super().__init__(f"{what}: {status_str(status)} ({status})" if what else status_str(status))
+        detail = ""
+        if status == LCS_ERR_DEVICE:
+            detail = " [" + _lib.lcs_last_error().decode(errors="replace") + "]"
+        msg = f"{what}: {status_str(status)} ({status})" if what else status_str(status)
+        super().__init__(msg + detail)
 
 
 class lcs_alphabet(ctypes.Structure):
@@ -76,6 +80,8 @@ def _load() -> ctypes.CDLL:
     lib.lcs_status_str.restype = ctypes.c_char_p
     lib.lcs_version.argtypes = []
     lib.lcs_version.restype = ctypes.c_char_p
+    lib.lcs_last_error.argtypes = []
+    lib.lcs_last_error.restype = ctypes.c_char_p
     lib.lcs_create.argtypes = [P(vp), i32, ctypes.c_size_t]
     lib.lcs_create.restype = i32
     lib.lcs_destroy.argtypes = [vp]
@@ -104,7 +110,7 @@ def _load() -> ctypes.CDLL:
     lib.lcs_batch_tracebacks.restype = i32
     lib.lcs_batch_info.argtypes = [vp, P(lcs_batch_stats)]
     lib.lcs_batch_info.restype = i32
-    lib.lcs_batch_time.argtypes = [vp, P(ctypes.c_float), P(ctypes.c_float)]
+    lib.lcs_batch_time.argtypes = [vp, i32, P(ctypes.c_float), P(ctypes.c_float)]
     lib.lcs_batch_time.restype = i32
     lib.lcs_batch_destroy.argtypes = [vp]
     lib.lcs_batch_destroy.restype = None
@@ -322,10 +328,12 @@ class Batch:
         _check(_lib.lcs_batch_info(self.h, ctypes.byref(s)), "lcs_batch_info")
         return s.as_dict()
 
-    def time(self) -> Tuple[float, float]:
-        """(total_ms, fill_ms) of one run, from HIP events on the batch's stream."""
+    def time(self, eager: bool = False) -> Tuple[float, float]:
+        """(total_ms, fill_ms) of one run from HIP events on the batch's stream;
+        fill_ms is -1 for a graph replay (eager=False on a graph batch)."""
         t, f = ctypes.c_float(), ctypes.c_float()
-        _check(_lib.lcs_batch_time(self.h, ctypes.byref(t), ctypes.byref(f)), "lcs_batch_time")
+        _check(_lib.lcs_batch_time(self.h, int(eager), ctypes.byref(t), ctypes.byref(f)),
+               "lcs_batch_time")
         return float(t.value), float(f.value)
 
     def close(self) -> None:
