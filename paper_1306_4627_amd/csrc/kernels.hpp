@@ -26,6 +26,8 @@ struct PrepArgs {
     uint32_t npairs;
     uint32_t *zero_words;      // counters/flags zeroed here
     uint64_t nzero;
+    uint64_t *zero64;          // traceback bitmaps zeroed here
+    uint64_t nzero64;
 };
 
 // Fill: one class (fixed words per lane), persistent waves.
@@ -47,8 +49,7 @@ struct FillArgs {
     uint64_t *out_len;
     uint64_t *ckpt;
     uint32_t *cbits;
-    uint64_t *xfer;
-    uint32_t *progress;        // per item: chunks completed (feeders only)
+    uint64_t *xfer;            // hand-over words, two per chunk per feeder (zeroed)
     uint32_t *queue;           // work counter (zeroed before the launch)
     uint32_t *error;           // set to 1 when a bounded wait runs out
     uint32_t item_begin;
@@ -58,16 +59,18 @@ struct FillArgs {
     int32_t ckpt_every;        // steps between checkpoints (traceback only)
 };
 
-// Traceback: one wave per pair, persistent.
+// Traceback walk: one wave per pair, persistent.  The walk records the rows
+// where it takes a diagonal step in a per-pair bitmap over X (bit r of word
+// w stands for row 64*w + r + 1); k_emit turns the bitmap into bytes.
 struct TbArgs {
     const uint8_t *xcodes;
-    const uint8_t *xbytes;
     const uint64_t *pair_xoff;
     const uint32_t *pair_m;
     const uint32_t *pair_n;
-    const uint64_t *pair_out;  // offset of each pair's string in `out`
-    const uint64_t *out_len;
-    const uint16_t *ystream;   // per class: code * (words_per_lane * 512)
+    const uint64_t *pair_diag;  // first bitmap word of each pair
+    uint64_t *diag;             // bitmaps (zeroed before the launch)
+    const uint16_t *ystream;    // per class: code * (words_per_lane * 512)
+    const uint32_t *it_T;
     const uint64_t *it_ck;
     const uint64_t *it_cb;
     const uint32_t *ln_skew;
@@ -78,17 +81,32 @@ struct TbArgs {
     const uint32_t *tb_item;
     const uint32_t *tb_lane0;
     uint32_t ntb;
-    uint8_t *out;
     uint32_t *queue;
     int32_t sigma;
     int32_t ckpt_every;
+    int32_t nb;                 // tiles recomputed together (one per lane)
+};
+
+// Emit: bitmap of diagonal rows -> LCS bytes (X symbols in row order).
+struct EmitArgs {
+    const uint8_t *xbytes;
+    const uint64_t *pair_xoff;
+    const uint32_t *pair_m;
+    const uint32_t *pair_n;
+    const uint64_t *pair_diag;
+    const uint64_t *diag;
+    const uint64_t *pair_out;
+    const uint64_t *out_len;
+    uint8_t *out;
+    uint32_t npairs;
+    uint32_t *error;            // set to 2 when a bitmap disagrees with the length
 };
 
 constexpr int kFillBlock = 256;   // four independent waves per work-group
 constexpr int kTbBlock = 256;
 
 size_t fill_lds_bytes(int wpl, int sigma);
-size_t tb_lds_bytes(int wpl, int sigma, int ckpt_every);
+size_t tb_lds_bytes(int wpl, int sigma, int ckpt_every, int nb);
 
 const void *fill_symbol(int wpl, bool tb);
 const void *tb_symbol(int wpl);
@@ -96,5 +114,6 @@ const void *tb_symbol(int wpl);
 hipError_t launch_prep(const PrepArgs &a, uint64_t xbytes_n, hipStream_t s);
 hipError_t launch_fill(int wpl, bool traceback, const FillArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_tb(int wpl, const TbArgs &a, uint32_t grid, hipStream_t s);
+hipError_t launch_emit(const EmitArgs &a, hipStream_t s);
 
 }  // namespace lcs

@@ -46,9 +46,10 @@ struct ClassDev {
     uint64_t *ckpt = nullptr;
     uint32_t *cbits = nullptr;
     uint64_t *xfer = nullptr;
-    uint32_t *progress = nullptr;
+    uint32_t *plain_ctr = nullptr;     // plain mode: two queue counters per pair
     uint32_t *q_fill = nullptr, *q_tb = nullptr;
     uint32_t fill_grid = 1, tb_grid = 1;
+    int nb = 1;                        // traceback tiles recomputed together
     // plain mode: one launch per pair
     std::vector<uint32_t> pl_pair;     // pair of each launch
     std::vector<uint32_t> pl_begin, pl_end, pl_tb;  // item range, index in tb list
@@ -86,6 +87,9 @@ struct lcs_batch {
     uint8_t *lut = nullptr, *xbytes = nullptr, *xcodes = nullptr, *ybytes = nullptr;
     uint64_t xarena = 0, yarena = 0;
     uint64_t *pair_xoff = nullptr, *pair_yoff = nullptr, *pair_out = nullptr, *out_len = nullptr;
+    uint64_t *pair_diag = nullptr, *diag = nullptr;   // diag lives in zero64
+    uint64_t diag_words = 0;
+    std::vector<uint64_t> diag_off_host;
     uint32_t *pair_m = nullptr, *pair_n = nullptr;
     uint64_t *seg_yoff = nullptr, *seg_begin = nullptr, *seg_len = nullptr;
     uint32_t *seg_n = nullptr, *seg_pre = nullptr;
@@ -94,6 +98,8 @@ struct lcs_batch {
     uint8_t *out = nullptr;
     uint32_t *zero = nullptr;
     uint64_t nzero = 0;
+    uint64_t *zero64 = nullptr;
+    uint64_t nzero64 = 0;
     uint32_t *error = nullptr;
     std::vector<ClassDev> cls;
     hipGraph_t graph = nullptr;
@@ -304,6 +310,7 @@ static size_t carve(lcs_batch *b, char *base) {
     b->pair_yoff = cv.take<uint64_t>(np + 1);
     b->pair_out = cv.take<uint64_t>(np + 1);
     b->out_len = cv.take<uint64_t>(np + 1);
+    b->pair_diag = cv.take<uint64_t>(np + 1);
     b->pair_m = cv.take<uint32_t>(np + 1);
     b->pair_n = cv.take<uint32_t>(np + 1);
     const size_t ns = p.segs.size();
@@ -315,18 +322,26 @@ static size_t carve(lcs_batch *b, char *base) {
     b->seg_shift = cv.take<uint8_t>(ns + 1);
     b->ystream = cv.take<uint16_t>(p.ys_elems + 64);
     b->out = cv.take<uint8_t>(b->out_bytes + 64);
-    // zeroed words: per class fill/tb counters, per-pair plain counters,
-    // per item progress flags, error flag
+    // zeroed before every pass, 32-bit: error word, then per class the fill
+    // and traceback queue counters and (plain mode) two counters per pair
     b->cls.resize(p.classes.size());
-    uint64_t nz = 1;   // error word first
+    uint64_t nz = 1;
     for (size_t ci = 0; ci < p.classes.size(); ++ci) {
         const ClassPlan &C = p.classes[ci];
-        nz += 2 + C.it_T.size();
+        nz += 2;
         if (b->plain) nz += 2 * C.tb_pair.size();
     }
     b->zero = cv.take<uint32_t>(nz);
     b->nzero = nz;
     b->error = b->zero;
+    // zeroed before every pass, 64-bit: traceback bitmaps, then the carry
+    // hand-over words of every class
+    uint64_t nz64 = (b->flags & LCS_WANT_TRACEBACK) ? b->diag_words : 0;
+    for (const ClassPlan &C : p.classes) nz64 += C.xf_words;
+    b->zero64 = cv.take<uint64_t>(nz64 + 1);
+    b->nzero64 = nz64;
+    b->diag = b->zero64;
+    uint64_t z64 = (b->flags & LCS_WANT_TRACEBACK) ? b->diag_words : 0;
     uint64_t zc = 1;
     for (size_t ci = 0; ci < p.classes.size(); ++ci) {
         const ClassPlan &C = p.classes[ci];
@@ -349,12 +364,12 @@ static size_t carve(lcs_batch *b, char *base) {
         D.tb_lane0 = cv.take<uint32_t>(D.ntb + 1);
         D.ckpt = cv.take<uint64_t>(C.ck_words + 1);
         D.cbits = cv.take<uint32_t>(C.cb_words + 1);
-        D.xfer = cv.take<uint64_t>(C.xf_words + 1);
+        D.xfer = b->zero64 ? b->zero64 + z64 : nullptr;
+        z64 += C.xf_words;
         D.q_fill = b->zero ? b->zero + zc : nullptr;
         D.q_tb = b->zero ? b->zero + zc + 1 : nullptr;
         zc += 2;
-        D.progress = b->zero ? b->zero + zc : nullptr;
-        zc += D.nitems;
+        D.plain_ctr = b->zero ? b->zero + zc : nullptr;
         if (b->plain) zc += 2 * D.ntb;
     }
     return cv.off + 256;
@@ -415,6 +430,15 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         oo += std::min(pairs[k].m, pairs[k].n);
     }
     b->out_off_host[count] = oo;
+    b->diag_off_host.assign(count + 1, 0);
+    if (flags & LCS_WANT_TRACEBACK) {
+        uint64_t dw = 0;
+        for (uint64_t k = 0; k < count; ++k) {
+            b->diag_off_host[k] = dw;
+            dw += (pairs[k].m + 63) / 64;
+        }
+        b->diag_words = dw;
+    }
     b->xarena = xa;
     b->yarena = ya;
     b->out_bytes = (flags & LCS_WANT_TRACEBACK) ? oo : 0;
@@ -489,6 +513,7 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     UP(bp->pair_xoff, xoff.data(), count * 8);
     UP(bp->pair_yoff, yoff.data(), count * 8);
     UP(bp->pair_out, bp->out_off_host.data(), count * 8);
+    UP(bp->pair_diag, bp->diag_off_host.data(), count * 8);
     UP(bp->pair_m, hm.data(), count * 4);
     UP(bp->pair_n, hn.data(), count * 4);
     UP(bp->seg_yoff, s_yoff.data(), ns * 8);
@@ -517,7 +542,13 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         D.fill_grid = resident_grid(ctx, fill_symbol(C.wpl, cfg.traceback),
                                     fill_lds_bytes(C.wpl, sigma), (D.nitems + 3) / 4,
                                     cap > 0 ? (cap + 3) / 4 : 0);
-        D.tb_grid = resident_grid(ctx, tb_symbol(C.wpl), tb_lds_bytes(C.wpl, sigma, cfg.ckpt),
+        // tiles per recompute batch: as many as fit 32 KiB of LDS per wave
+        {
+            const size_t tile = (size_t)cfg.ckpt * C.wpl * 16;
+            int nb = (int)((32 * 1024 - 2048) / tile);
+            D.nb = nb < 1 ? 1 : (nb > 8 ? 8 : nb);
+        }
+        D.tb_grid = resident_grid(ctx, tb_symbol(C.wpl), tb_lds_bytes(C.wpl, sigma, cfg.ckpt, D.nb),
                                   (D.ntb + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
         if (bp->plain) {
             // one launch per pair: items of a pair are consecutive
@@ -569,6 +600,8 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
     pa.npairs = (uint32_t)b->npairs;
     pa.zero_words = b->zero;
     pa.nzero = b->nzero;
+    pa.zero64 = b->zero64;
+    pa.nzero64 = b->nzero64;
     if (events) HIP_TRY(hipEventRecord(b->ev[0], s));
     HIP_TRY(launch_prep(pa, b->xarena + 64, s));
     if (events) HIP_TRY(hipEventRecord(b->ev[1], s));
@@ -594,7 +627,6 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         fa.ckpt = D.ckpt;
         fa.cbits = D.cbits;
         fa.xfer = D.xfer;
-        fa.progress = D.progress;
         fa.queue = D.q_fill;
         fa.error = b->error;
         fa.item_begin = 0;
@@ -608,13 +640,13 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         const ClassDev &D = b->cls[ci];
         TbArgs ta{};
         ta.xcodes = b->xcodes;
-        ta.xbytes = b->xbytes;
         ta.pair_xoff = b->pair_xoff;
         ta.pair_m = b->pair_m;
         ta.pair_n = b->pair_n;
-        ta.pair_out = b->pair_out;
-        ta.out_len = b->out_len;
+        ta.pair_diag = b->pair_diag;
+        ta.diag = b->diag;
         ta.ystream = b->ystream;
+        ta.it_T = D.it_T;
         ta.it_ck = D.it_ck;
         ta.it_cb = D.it_cb;
         ta.ln_skew = D.ln_skew;
@@ -625,12 +657,24 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         ta.tb_item = D.tb_item;
         ta.tb_lane0 = D.tb_lane0;
         ta.ntb = D.ntb;
-        ta.out = b->out;
         ta.queue = D.q_tb;
         ta.sigma = b->sigma;
         ta.ckpt_every = b->ckpt;
+        ta.nb = D.nb;
         return ta;
     };
+    EmitArgs ea{};
+    ea.xbytes = b->xbytes;
+    ea.pair_xoff = b->pair_xoff;
+    ea.pair_m = b->pair_m;
+    ea.pair_n = b->pair_n;
+    ea.pair_diag = b->pair_diag;
+    ea.diag = b->diag;
+    ea.pair_out = b->pair_out;
+    ea.out_len = b->out_len;
+    ea.out = b->out;
+    ea.npairs = (uint32_t)b->npairs;
+    ea.error = b->error;
     if (!b->plain) {
         for (size_t ci = 0; ci < b->cls.size(); ++ci) {
             const ClassDev &D = b->cls[ci];
@@ -638,18 +682,20 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
             HIP_TRY(launch_fill(D.wpl, tb, fill_args(ci), D.fill_grid, s));
         }
         if (events) HIP_TRY(hipEventRecord(b->ev[2], s));
-        if (tb)
+        if (tb) {
             for (size_t ci = 0; ci < b->cls.size(); ++ci) {
                 const ClassDev &D = b->cls[ci];
                 if (!D.ntb) continue;
                 HIP_TRY(launch_tb(D.wpl, tb_args(ci), D.tb_grid, s));
             }
+            HIP_TRY(launch_emit(ea, s));
+        }
     } else {
         // plain per-pair: every pair gets its own fill launch (and its own
         // traceback launch), in order
         for (size_t ci = 0; ci < b->cls.size(); ++ci) {
             const ClassDev &D = b->cls[ci];
-            uint32_t *ctr = D.progress + D.nitems;
+            uint32_t *ctr = D.plain_ctr;
             for (size_t k = 0; k < D.pl_pair.size(); ++k) {
                 FillArgs fa = fill_args(ci);
                 fa.item_begin = D.pl_begin[k];
@@ -665,6 +711,16 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
                     ta.ntb = 1;
                     ta.queue = ctr + 2 * k + 1;
                     HIP_TRY(launch_tb(D.wpl, ta, 1, s));
+                    const uint32_t pr = D.pl_pair[k];
+                    EmitArgs e1 = ea;
+                    e1.pair_xoff += pr;
+                    e1.pair_m += pr;
+                    e1.pair_n += pr;
+                    e1.pair_diag += pr;
+                    e1.pair_out += pr;
+                    e1.out_len += pr;
+                    e1.npairs = 1;
+                    HIP_TRY(launch_emit(e1, s));
                 }
             }
         }
@@ -721,8 +777,9 @@ static lcs_status finish(lcs_batch *b) {
     uint32_t err = 0;
     HIP_TRY(hipMemcpy(&err, b->error, 4, hipMemcpyDeviceToHost));
     if (err) {
-        std::snprintf(g_last_error, sizeof g_last_error,
-                      "a carry hand-over wait ran out of polls (kernel error flag %u)", err);
+        std::snprintf(g_last_error, sizeof g_last_error, "kernel error flag %u (%s)", err,
+                      (err & 1u) ? "a carry hand-over wait ran out of polls"
+                                 : "a traceback disagrees with its length");
         return LCS_ERR_DEVICE;
     }
     return LCS_OK;

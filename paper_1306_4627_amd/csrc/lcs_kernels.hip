@@ -77,6 +77,7 @@ __global__ void k_zero(PrepArgs a) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t k = tid; k < a.npairs; k += stride) a.out_len[k] = 0;
     for (uint64_t k = tid; k < a.nzero; k += stride) a.zero_words[k] = 0;
+    for (uint64_t k = tid; k < a.nzero64; k += stride) a.zero64[k] = 0;
 }
 
 hipError_t launch_prep(const PrepArgs &a, uint64_t xbytes_n, hipStream_t s) {
@@ -130,6 +131,63 @@ __device__ __forceinline__ void column_step(uint32_t (&vlo)[WPL], uint32_t (&vhi
             : [vlo] "+v"(vlo[q]), [vhi] "+v"(vhi[q]), [c] "+s"(carry), [ulo] "=&v"(t0),
               [uhi] "=&v"(t1)
             : [mlo] "v"(mlo), [mhi] "v"(mhi));
+    }
+}
+
+// Make a value the compiler cannot prove wave-uniform live in SGPRs again (a
+// no-op when it already does).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Sixteen stream values (two per dword) starting at step t0.
+__device__ __forceinline__ void load16(const uint16_t *ys, uint32_t t0, uint32_t (&d)[8]) {
+    const uint16_t *p = ys + t0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) d[e] = (uint32_t)p[2 * e] | ((uint32_t)p[2 * e + 1] << 16);
+}
+
+// Sixteen column steps t..t+15 of one lane.  The carry-in lane mask of a
+// step is the carry-out mask of the previous step shifted up by one lane,
+// with segment starts cleared; with CHAIN, lane 0 takes the hand-over bit of
+// the feeding item (inbits, one bit per step) and lane 63's carry-out is
+// collected into outbits for the next item.  With TB, every lane's carry-in
+// bits are accumulated (newest in bit 0) and stored every 32 steps.
+template <int WPL, bool TB, bool CHAIN>
+__device__ __forceinline__ void run16(const uint32_t (&Yg)[8], uint32_t t, const char *lanecol,
+                                      uint64_t notstart, uint64_t &cmask, uint32_t &acc,
+                                      uint32_t *cbp, uint32_t (&vlo)[WPL], uint32_t (&vhi)[WPL],
+                                      uint64_t &inbits, uint64_t &outbits) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const uint32_t off = (e & 1) ? (Yg[e >> 1] >> 16) : (Yg[e >> 1] & 0xffffu);
+        const char *row = lanecol + off;
+        uint64_t M[WPL];
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) M[q] = *(const uint64_t *)(row + q * 512);
+        uint64_t cm = cmask;
+        if (CHAIN) {
+            cm |= inbits & 1ull;
+            inbits >>= 1;
+        }
+        if (TB) {
+            uint32_t cj;
+            acc = __builtin_addc(acc, acc, (uint32_t)__builtin_amdgcn_inverse_ballot_w64(cm), &cj);
+            if (e == 15 && (t & 16u)) cbp[(size_t)((t + e) >> 5) * 64] = acc;
+        }
+        column_step<WPL>(vlo, vhi, M, cm);
+        if (CHAIN) {
+            outbits = (outbits >> 1) | (cm & 0x8000000000000000ull);
+            // pin the accumulation to this step: sunk to its single use,
+            // it would keep every step's carry mask alive until the chunk end
+            asm volatile("" : "+s"(outbits), "+s"(inbits));
+        }
+        cmask = (cm << 1) & notstart;
+        // keep the scheduler from spreading the scalar work of many steps
+        // across each other (it would hold dozens of masks live)
+        if ((e & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -207,75 +265,77 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
             ckp = a.ckpt + a.it_ck[item] + lane;
             cbp = a.cbits + a.it_cb[item] + lane;
         }
+        // Carry hand-over between chained items: chunk c of a feeder is two
+        // 64-bit words, each a 32-bit tag (c + 1) above 32 carry bits, written
+        // with relaxed agent-scope atomic stores; the consumer accepts a word
+        // once its tag matches.  The words carry their own validity, so no
+        // release/acquire fence (an L2 write-back on this chip) is needed;
+        // the buffer is zeroed before every pass.
         uint64_t *xf_out = feeds ? a.xfer + a.it_xf[item] : nullptr;
-        const uint64_t *xf_in = prev >= 0 ? a.xfer + a.it_xf[prev] : nullptr;
+        uint64_t *xf_in = prev >= 0 ? a.xfer + a.it_xf[prev] : nullptr;
         bool aborted = false;
-        // stream values for the next 8 steps, two per dword
-        uint32_t yw[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) yw[e] = (uint32_t)ys[2 * e] | ((uint32_t)ys[2 * e + 1] << 16);
+        // Stream values, two per dword, in a ring of four 16-step groups; the
+        // group 32 steps ahead is requested before the current one is used,
+        // so the stream's memory latency hides behind two groups of work.
+        uint32_t Y0[8], Y1[8], Y2[8], Y3[8];
+        load16(ys, 0, Y0);
+        load16(ys, 16, Y1);
+        const bool chain = prev >= 0 || feeds;
+        uint64_t pw0 = 0, pw1 = 0;   // hand-over words requested one group early
 
         for (uint32_t c = 0; c < nch; ++c) {
-            uint64_t inbits = 0;
+            uint64_t inbits = 0, outbits = 0;
             if (prev >= 0 && c > 0) {
-                // bounded wait for the feeding item to finish chunk c-1
+                uint64_t w0 = uniform64(pw0), w1 = uniform64(pw1);
                 uint32_t spins = 0;
-                for (;;) {
-                    uint32_t got = __hip_atomic_load(a.progress + prev, __ATOMIC_ACQUIRE,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-                    got = __builtin_amdgcn_readfirstlane(got);
-                    if (got >= c) break;
+                while ((uint32_t)(w0 >> 32) != c || (uint32_t)(w1 >> 32) != c) {
+                    // bounded wait for the feeding item to finish chunk c-1
                     if (++spins > a.spin_limit) { aborted = true; break; }
                     __builtin_amdgcn_s_sleep(1);
+                    w0 = uniform64(__hip_atomic_load(xf_in + 2 * (c - 1), __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT));
+                    w1 = uniform64(__hip_atomic_load(xf_in + 2 * (c - 1) + 1, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT));
                 }
                 if (aborted) break;
-                const uint64_t w = __hip_atomic_load(xf_in + (c - 1), __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)w);
-                const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(w >> 32));
-                inbits = ((uint64_t)hi << 32) | lo;
+                inbits = (w1 << 32) | (w0 & 0xffffffffull);
             }
             if (TB && ((c * 64u) % (uint32_t)a.ckpt_every) == 0) {
                 uint64_t *dst = ckp + (size_t)((c * 64u) / (uint32_t)a.ckpt_every) * RS;
 #pragma unroll
                 for (int q = 0; q < WPL; ++q) dst[q * 64] = ((uint64_t)vhi[q] << 32) | vlo[q];
             }
-            uint64_t outbits = 0;
-#pragma unroll 1
-            for (int g = 0; g < 8; ++g) {
-                const uint32_t t = c * 64u + (uint32_t)g * 8u;
-                uint32_t yn[4];
-                const uint16_t *nx = ys + t + 8;
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    yn[e] = (uint32_t)nx[2 * e] | ((uint32_t)nx[2 * e + 1] << 16);
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const uint32_t off = (e & 1) ? (yw[e >> 1] >> 16) : (yw[e >> 1] & 0xffffu);
-                    const char *row = lanecol + off;
-                    uint64_t M[WPL];
-#pragma unroll
-                    for (int q = 0; q < WPL; ++q) M[q] = *(const uint64_t *)(row + q * 512);
-                    uint64_t cm = cmask | (inbits & 1ull);
-                    inbits >>= 1;
-                    if (TB) {
-                        uint32_t cj;
-                        acc = __builtin_addc(acc, acc,
-                                             (uint32_t)__builtin_amdgcn_inverse_ballot_w64(cm), &cj);
-                        if ((e & 7) == 7 && (g & 3) == 3)
-                            cbp[(size_t)((t + e) >> 5) * 64] = acc;
-                    }
-                    column_step<WPL>(vlo, vhi, M, cm);
-                    outbits = (outbits >> 1) | (cm & 0x8000000000000000ull);
-                    cmask = (cm << 1) & notstart;
+            const uint32_t t = c * 64u;
+            if (chain) {
+                load16(ys, t + 32, Y2);
+                run16<WPL, TB, true>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                load16(ys, t + 48, Y3);
+                run16<WPL, TB, true>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                load16(ys, t + 64, Y0);
+                run16<WPL, TB, true>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                load16(ys, t + 80, Y1);
+                if (prev >= 0) {
+                    pw0 = __hip_atomic_load(xf_in + 2 * c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    pw1 = __hip_atomic_load(xf_in + 2 * c + 1, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
-#pragma unroll
-                for (int e = 0; e < 4; ++e) yw[e] = yn[e];
-            }
-            if (feeds && lane == 0) {
-                xf_out[c] = outbits;
-                __hip_atomic_store(a.progress + item, c + 1, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                run16<WPL, TB, true>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                if (feeds && lane == 0) {
+                    const uint64_t tag = (uint64_t)(c + 1) << 32;
+                    __hip_atomic_store(xf_out + 2 * c, tag | (outbits & 0xffffffffull),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(xf_out + 2 * c + 1, tag | (outbits >> 32), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                }
+            } else {
+                load16(ys, t + 32, Y2);
+                run16<WPL, TB, false>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                load16(ys, t + 48, Y3);
+                run16<WPL, TB, false>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                load16(ys, t + 64, Y0);
+                run16<WPL, TB, false>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                load16(ys, t + 80, Y1);
+                run16<WPL, TB, false>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
             }
         }
         if (aborted) {
@@ -334,13 +394,16 @@ hipError_t launch_fill(int wpl, bool tb, const FillArgs &a, uint32_t grid, hipSt
 // traceback
 // --------------------------------------------------------------------------
 
-__host__ __device__ static inline size_t tb_wave_words(int wpl, int sigma, int K) {
-    // match masks of one band, the V history of one tile, the tile's codes
-    return (size_t)(sigma + 1) * wpl + (size_t)K * wpl + ((size_t)K + 7) / 8;
+// Per-wave LDS of the walk, in 64-bit words: the band's match masks, NB
+// recomputed tiles of (V, M) words, the tiles' stream values and carry-in
+// words.
+__host__ __device__ static inline size_t tb_wave_words(int wpl, int sigma, int K, int nb) {
+    return (size_t)(sigma + 1) * wpl + (size_t)nb * K * wpl * 2 + ((size_t)nb * K + 3) / 4 +
+           ((size_t)nb * K / 32 + 1 + 1) / 2;
 }
 
-size_t tb_lds_bytes(int wpl, int sigma, int K) {
-    return (size_t)(kTbBlock / 64) * tb_wave_words(wpl, sigma, K) * sizeof(uint64_t);
+size_t tb_lds_bytes(int wpl, int sigma, int K, int nb) {
+    return (size_t)(kTbBlock / 64) * tb_wave_words(wpl, sigma, K, nb) * sizeof(uint64_t);
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -348,6 +411,14 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// One wave per pair.  The walk of section I.D from (m, n): inside column j
+// the walk climbs to the highest row r <= i whose bit is set in
+// PM[y_j] | ~V_j; a match there is a diagonal step (emit x_r, go to
+// (r-1, j-1)), otherwise the column steps left at r.  V_j for the rows of
+// the current band (the rows one lane of the fill held) is recomputed from
+// the fill's checkpoints: NB consecutive step ranges ("tiles") of the band
+// at a time, one lane per tile, each from its own checkpoint and the band's
+// stored carry-in bits.
 template <int WPL>
 __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
     extern __shared__ uint64_t smem[];
@@ -355,10 +426,12 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
     const int wv = threadIdx.x >> 6;
     const int sig1 = a.sigma + 1;
     const uint32_t K = (uint32_t)a.ckpt_every;
-    uint64_t *pmw = smem + (size_t)wv * tb_wave_words(WPL, a.sigma, (int)K);
-    uint64_t *tv = pmw + sig1 * WPL;
-    uint8_t *ty = (uint8_t *)(tv + (size_t)K * WPL);
-    const uint32_t BAND = 64u * WPL;
+    const uint32_t NB = (uint32_t)a.nb;
+    uint64_t *pmw = smem + (size_t)wv * tb_wave_words(WPL, a.sigma, (int)K, (int)NB);
+    uint64_t *tiles = pmw + sig1 * WPL;                       // [slot][o][q][V,M]
+    uint16_t *ystage = (uint16_t *)(tiles + (size_t)NB * K * WPL * 2);
+    uint32_t *cbstage = (uint32_t *)(ystage + (((size_t)NB * K + 3) / 4) * 4);
+    constexpr uint32_t BAND = 64u * WPL;
     constexpr uint32_t kShift = 9 + (WPL == 1 ? 0 : WPL == 2 ? 1 : WPL == 4 ? 2 : 3);
 
     for (;;) {
@@ -371,31 +444,32 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
         const uint32_t lane0 = a.tb_lane0[ticket];
         const uint32_t m = a.pair_m[p];
         const uint32_t n = a.pair_n[p];
-        int64_t k = (int64_t)a.out_len[p];
         const uint8_t *xc = a.xcodes + a.pair_xoff[p];
-        const uint8_t *xb = a.xbytes + a.pair_xoff[p];
-        uint8_t *out = a.out + a.pair_out[p];
+        uint64_t *dg = a.diag + a.pair_diag[p];
 
         int64_t i = m, j = n;
-        int64_t band = -1, tile = -1;
-        uint32_t skew = 0, lanei = 0;
+        int64_t band = -1, kt_hi = -1, kt_lo = 0;
+        uint32_t skew = 0, Tw = 0;
         const uint16_t *ys = nullptr;
         const uint64_t *ck = nullptr;
         const uint32_t *cb = nullptr;
+        int64_t dwi = -1;          // bitmap word being filled
+        uint64_t dword = 0;
 
         while (i > 0 && j > 0) {
             const int64_t ell = (i - 1) / BAND;
             if (ell != band) {
                 band = ell;
-                tile = -1;
+                kt_hi = -1;
                 const uint32_t g = lane0 + (uint32_t)ell;
                 const uint32_t item = item0 + g / 64;
-                lanei = g % 64;
+                const uint32_t lanei = g % 64;
                 const size_t li = (size_t)item * 64 + lanei;
                 skew = a.ln_skew[li];
                 ys = a.ystream + a.ln_ys[li] - skew;
                 ck = a.ckpt + a.it_ck[item] + lanei;
                 cb = a.cbits + a.it_cb[item] + lanei;
+                Tw = a.it_T[item] / 32;
                 // match masks of this band's rows
                 for (int e = lane; e < sig1 * WPL; e += 64) pmw[e] = 0;
                 wave_lds_sync();
@@ -411,50 +485,65 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
             }
             const int64_t t = (j - 1) + (int64_t)skew;
             const int64_t kt = t / K;
-            if (kt != tile) {
-                // recompute V for steps kt*K .. t of this lane from its checkpoint
-                uint64_t V[WPL];
+            if (kt > kt_hi || kt < kt_lo) {
+                // recompute tiles kt-NB+1 .. kt of this band, one lane each
+                kt_hi = kt;
+                kt_lo = kt - (int64_t)NB + 1 < 0 ? 0 : kt - (int64_t)NB + 1;
+                const uint32_t sbase = (uint32_t)kt_lo * K;
+                const uint32_t nsteps = (uint32_t)(kt_hi - kt_lo + 1) * K;
+                for (uint32_t e = lane; e < nsteps; e += 64) ystage[e] = ys[sbase + e];
+                for (uint32_t e = lane; e < nsteps / 32; e += 64) {
+                    const uint32_t w = (sbase >> 5) + e;
+                    cbstage[e] = w < Tw ? cb[(size_t)w * 64] : 0u;
+                }
+                wave_lds_sync();
+                const uint32_t slot = (uint32_t)lane;
+                if ((int64_t)slot <= kt_hi - kt_lo) {
+                    const int64_t ktl = kt_hi - slot;
+                    uint64_t V[WPL];
 #pragma unroll
-                for (int q = 0; q < WPL; ++q) V[q] = ck[((size_t)kt * WPL + q) * 64];
-                const uint32_t t0 = (uint32_t)(kt * K);
-                for (uint32_t tt = t0; tt <= (uint32_t)t; ++tt) {
-                    const uint32_t y = (uint32_t)ys[tt] >> kShift;
-                    uint32_t carry = (cb[(size_t)(tt >> 5) * 64] >> (31 - (tt & 31))) & 1u;
+                    for (int q = 0; q < WPL; ++q) V[q] = ck[((size_t)ktl * WPL + q) * 64];
+                    const uint32_t e0 = (uint32_t)(ktl - kt_lo) * K;
+                    uint64_t *tdst = tiles + (size_t)slot * K * WPL * 2;
+#pragma unroll 4
+                    for (uint32_t o = 0; o < K; ++o) {
+                        const uint32_t e = e0 + o;
+                        const uint32_t code = (uint32_t)ystage[e] >> kShift;
+                        uint32_t carry = (cbstage[e >> 5] >> (31 - (e & 31))) & 1u;
 #pragma unroll
-                    for (int q = 0; q < WPL; ++q) {
-                        const uint64_t M = pmw[y * WPL + q];
-                        const uint64_t v = V[q];
-                        const uint64_t U = v & M;
-                        uint32_t c1, c2;
-                        const uint32_t slo = __builtin_addc((uint32_t)v, (uint32_t)U, carry, &c1);
-                        const uint32_t shi =
-                            __builtin_addc((uint32_t)(v >> 32), (uint32_t)(U >> 32), c1, &c2);
-                        carry = c2;
-                        V[q] = ((((uint64_t)shi) << 32) | slo) | (v & ~M);
-                    }
-                    if (lane == 0) {
-#pragma unroll
-                        for (int q = 0; q < WPL; ++q) tv[(size_t)(tt - t0) * WPL + q] = V[q];
-                        ty[tt - t0] = (uint8_t)y;
+                        for (int q = 0; q < WPL; ++q) {
+                            const uint64_t M = pmw[code * WPL + q];
+                            const uint64_t v = V[q];
+                            const uint64_t U = v & M;
+                            uint32_t c1, c2;
+                            const uint32_t slo =
+                                __builtin_addc((uint32_t)v, (uint32_t)U, carry, &c1);
+                            const uint32_t shi =
+                                __builtin_addc((uint32_t)(v >> 32), (uint32_t)(U >> 32), c1, &c2);
+                            carry = c2;
+                            V[q] = ((((uint64_t)shi) << 32) | slo) | (v & ~M);
+                            tdst[((size_t)o * WPL + q) * 2] = V[q];
+                            tdst[((size_t)o * WPL + q) * 2 + 1] = M;
+                        }
                     }
                 }
                 wave_lds_sync();
-                tile = kt;
             }
-            // walk inside the tile
+            // walk inside the resident tiles of this band
             int64_t tc = t;
-            const int64_t tlo = kt * K;
+            const int64_t tlo = kt_lo * K;
             for (;;) {
-                const uint32_t o = (uint32_t)(tc - tlo);
-                const uint32_t y = ty[o];
+                const uint32_t slot = (uint32_t)(kt_hi - tc / K);
+                const uint32_t o = (uint32_t)(tc % K);
+                const uint64_t *col = tiles + ((size_t)slot * K + o) * WPL * 2;
                 const uint32_t rl = (uint32_t)((i - 1) - ell * BAND);
                 int q = (int)(rl / 64);
                 int b = (int)(rl % 64);
                 bool found = false;
                 uint64_t Mw = 0, cand = 0;
                 for (;;) {
-                    Mw = pmw[y * WPL + q];
-                    const uint64_t Vw = tv[(size_t)o * WPL + q];
+                    const uint64_t Vw = col[q * 2];
+                    Mw = col[q * 2 + 1];
                     const uint64_t low = (b == 63) ? ~0ull : ((2ull << b) - 1);
                     cand = (Mw | ~Vw) & low;
                     if (cand) { found = true; break; }
@@ -469,8 +558,13 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
                 const int r = 63 - __builtin_clzll(cand);
                 const int64_t row = ell * BAND + (int64_t)q * 64 + r + 1;
                 if ((Mw >> r) & 1ull) {
-                    --k;
-                    if (lane == 0 && k >= 0) out[k] = xb[row - 1];
+                    const int64_t w = (row - 1) >> 6;
+                    if (w != dwi) {
+                        if (dwi >= 0 && dword && lane == 0) dg[dwi] = dword;
+                        dwi = w;
+                        dword = 0;
+                    }
+                    dword |= 1ull << ((row - 1) & 63);
                     i = row - 1;
                 } else {
                     i = row;
@@ -482,7 +576,55 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
                 if (tc < tlo) break;
             }
         }
+        if (dwi >= 0 && dword && lane == 0) dg[dwi] = dword;
     }
+}
+
+// One wave per pair: the bitmap of diagonal rows, read in row order, selects
+// the symbols of X that form the LCS.
+__global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (blockDim.x / 64);
+    for (uint32_t p = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); p < a.npairs;
+         p += waves) {
+        const uint32_t m = a.pair_m[p];
+        const uint32_t n = a.pair_n[p];
+        const uint64_t cap = m < n ? m : n;     // the pair's slot in `out`
+        const uint32_t W = (m + 63) / 64;
+        const uint64_t *bm = a.diag + a.pair_diag[p];
+        const uint8_t *x = a.xbytes + a.pair_xoff[p];
+        uint8_t *o = a.out + a.pair_out[p];
+        uint64_t base = 0;
+        for (uint32_t w0 = 0; w0 < W; w0 += 64) {
+            const uint32_t w = w0 + lane;
+            uint64_t bits = w < W ? bm[w] : 0ull;
+            const uint32_t c = (uint32_t)__builtin_popcountll(bits);
+            uint32_t incl = c;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t up = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += up;
+            }
+            const uint32_t total = __shfl(incl, 63, 64);
+            uint64_t pos = base + incl - c;
+            while (bits) {
+                const int r = __builtin_ctzll(bits);
+                if (pos < cap) o[pos] = x[(size_t)w * 64 + r];
+                ++pos;
+                bits &= bits - 1;
+            }
+            base += total;
+        }
+        if (lane == 0 && base != a.out_len[p]) atomicOr(a.error, 2u);
+    }
+}
+
+hipError_t launch_emit(const EmitArgs &a, hipStream_t s) {
+    if (!a.npairs) return hipSuccess;
+    uint32_t blocks = (a.npairs + 3) / 4;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 const void *tb_symbol(int wpl) {
@@ -495,7 +637,7 @@ const void *tb_symbol(int wpl) {
 }
 
 hipError_t launch_tb(int wpl, const TbArgs &a, uint32_t grid, hipStream_t s) {
-    const size_t lds = tb_lds_bytes(wpl, a.sigma, a.ckpt_every);
+    const size_t lds = tb_lds_bytes(wpl, a.sigma, a.ckpt_every, a.nb);
     switch (wpl) {
         case 1: hipLaunchKernelGGL((k_traceback<1>), dim3(grid), dim3(kTbBlock), lds, s, a); break;
         case 2: hipLaunchKernelGGL((k_traceback<2>), dim3(grid), dim3(kTbBlock), lds, s, a); break;

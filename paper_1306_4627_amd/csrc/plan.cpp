@@ -180,7 +180,7 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
                 C.ck_words += ceil_div(t, (uint64_t)cfg.ckpt) * (uint64_t)wpl * kLanes;
                 C.cb_words += (t / kCbitsPer) * kLanes;
             }
-            if (C.it_feeds[it]) C.xf_words += t / kChunk;
+            if (C.it_feeds[it]) C.xf_words += 2 * (t / kChunk);
         }
         // traceback order: largest m*n first
         std::vector<size_t> ord(C.tb_pair.size());
@@ -223,8 +223,11 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
         sg.pair = ps.pair;
         sg.pre = ps.pre;
         sg.begin = cursor;
-        // + one chunk: the fill reads the stream a few steps ahead
-        sg.len = (uint64_t)ps.pre + C.it_T[ps.last_item] + kChunk;
+        // + one chunk: the fill reads the stream a few steps ahead; with a
+        // traceback, whole checkpoint intervals are re-read
+        uint64_t Tr = C.it_T[ps.last_item];
+        if (cfg.traceback) Tr = ceil_div(Tr, (uint64_t)cfg.ckpt) * cfg.ckpt;
+        sg.len = (uint64_t)ps.pre + Tr + kChunk;
         sg.shift = shift_of(C.wpl);
         cursor += (sg.len + 63) / 64 * 64;
         seg_col0[ps.pair] = sg.begin + sg.pre;

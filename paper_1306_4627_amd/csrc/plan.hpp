@@ -54,7 +54,7 @@ struct ClassPlan {
     std::vector<uint8_t> it_feeds;    // 1 if lane 63 continues into the next item
     std::vector<uint64_t> it_ck;      // checkpoint base (uint64 units)
     std::vector<uint64_t> it_cb;      // carry-bit base (uint32 units)
-    std::vector<uint64_t> it_xf;      // carry hand-over base (uint64 units), for feeders
+    std::vector<uint64_t> it_xf;      // carry hand-over base (uint64 units, 2 per chunk), for feeders
     // lanes (item-major, kLanes per item)
     std::vector<int32_t> ln_pair;     // -1 = idle
     std::vector<uint32_t> ln_word0;   // first word of the pair held by the lane
