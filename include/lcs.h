@@ -86,7 +86,7 @@ typedef struct lcs_batch lcs_batch;
  *  words_per_lane  : 64-bit words of the bit-vector column held per lane
  *                    (1, 2, 4 or 8);
  *  ckpt_interval   : columns between stored bit-vector checkpoints for the
- *                    traceback (multiple of 64);
+ *                    traceback (64, 128 or 256);
  *  persistent_waves: cap on resident work-groups of the persistent kernels;
  *  plain           : 1 = no packing: one pair per work-group and one launch
  *                    per pair (the plain per-pair path, for comparison). */

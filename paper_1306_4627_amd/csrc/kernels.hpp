@@ -109,7 +109,7 @@ size_t fill_lds_bytes(int wpl, int sigma);
 size_t tb_lds_bytes(int wpl, int sigma, int ckpt_every, int nb);
 
 const void *fill_symbol(int wpl, bool tb);
-const void *tb_symbol(int wpl);
+const void *tb_symbol(int wpl, int ckpt_every);
 
 hipError_t launch_prep(const PrepArgs &a, uint64_t xbytes_n, hipStream_t s);
 hipError_t launch_fill(int wpl, bool traceback, const FillArgs &a, uint32_t grid, hipStream_t s);

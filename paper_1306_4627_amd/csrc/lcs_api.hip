@@ -175,7 +175,9 @@ static lcs_status check_tuning(const lcs_tuning *t) {
     if (t->words_per_lane != 0 && t->words_per_lane != 1 && t->words_per_lane != 2 &&
         t->words_per_lane != 4 && t->words_per_lane != 8)
         return LCS_ERR_ARG;
-    if (t->ckpt_interval < 0 || (t->ckpt_interval % 64) != 0) return LCS_ERR_ARG;
+    if (t->ckpt_interval != 0 && t->ckpt_interval != 64 && t->ckpt_interval != 128 &&
+        t->ckpt_interval != 256)
+        return LCS_ERR_ARG;
     if (t->persistent_waves < 0 || t->plain < 0 || t->plain > 1) return LCS_ERR_ARG;
     return LCS_OK;
 }
@@ -548,7 +550,7 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
             int nb = (int)((32 * 1024 - 2048) / tile);
             D.nb = nb < 1 ? 1 : (nb > 8 ? 8 : nb);
         }
-        D.tb_grid = resident_grid(ctx, tb_symbol(C.wpl), tb_lds_bytes(C.wpl, sigma, cfg.ckpt, D.nb),
+        D.tb_grid = resident_grid(ctx, tb_symbol(C.wpl, cfg.ckpt), tb_lds_bytes(C.wpl, sigma, cfg.ckpt, D.nb),
                                   (D.ntb + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
         if (bp->plain) {
             // one launch per pair: items of a pair are consecutive

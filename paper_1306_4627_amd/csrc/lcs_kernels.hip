@@ -406,6 +406,13 @@ size_t tb_lds_bytes(int wpl, int sigma, int K, int nb) {
     return (size_t)(kTbBlock / 64) * tb_wave_words(wpl, sigma, K, nb) * sizeof(uint64_t);
 }
 
+// Lane `idx` (wave-uniform) of a 64-bit per-lane value, as a scalar.
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int32_t idx) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, idx);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), idx);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -416,23 +423,23 @@ __device__ __forceinline__ void wave_lds_sync() {
 // PM[y_j] | ~V_j; a match there is a diagonal step (emit x_r, go to
 // (r-1, j-1)), otherwise the column steps left at r.  V_j for the rows of
 // the current band (the rows one lane of the fill held) is recomputed from
-// the fill's checkpoints: NB consecutive step ranges ("tiles") of the band
-// at a time, one lane per tile, each from its own checkpoint and the band's
-// stored carry-in bits.
-template <int WPL>
+// the fill's checkpoints: NB consecutive step ranges ("tiles", 2^LOGK steps
+// each) of the band at a time, one lane per tile, each from its own
+// checkpoint and the band's stored carry-in bits.
+template <int WPL, int LOGK>
 __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
     extern __shared__ uint64_t smem[];
+    constexpr uint32_t K = 1u << LOGK;
+    constexpr uint32_t BAND = 64u * WPL;
+    constexpr uint32_t kShift = 9 + (WPL == 1 ? 0 : WPL == 2 ? 1 : WPL == 4 ? 2 : 3);
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int sig1 = a.sigma + 1;
-    const uint32_t K = (uint32_t)a.ckpt_every;
     const uint32_t NB = (uint32_t)a.nb;
     uint64_t *pmw = smem + (size_t)wv * tb_wave_words(WPL, a.sigma, (int)K, (int)NB);
     uint64_t *tiles = pmw + sig1 * WPL;                       // [slot][o][q][V,M]
     uint16_t *ystage = (uint16_t *)(tiles + (size_t)NB * K * WPL * 2);
     uint32_t *cbstage = (uint32_t *)(ystage + (((size_t)NB * K + 3) / 4) * 4);
-    constexpr uint32_t BAND = 64u * WPL;
-    constexpr uint32_t kShift = 9 + (WPL == 1 ? 0 : WPL == 2 ? 1 : WPL == 4 ? 2 : 3);
 
     for (;;) {
         uint32_t ticket = 0;
@@ -447,17 +454,17 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
         const uint8_t *xc = a.xcodes + a.pair_xoff[p];
         uint64_t *dg = a.diag + a.pair_diag[p];
 
-        int64_t i = m, j = n;
-        int64_t band = -1, kt_hi = -1, kt_lo = 0;
+        int32_t i = (int32_t)m, j = (int32_t)n;
+        int32_t band = -1, kt_hi = -1, kt_lo = 0;
         uint32_t skew = 0, Tw = 0;
         const uint16_t *ys = nullptr;
         const uint64_t *ck = nullptr;
         const uint32_t *cb = nullptr;
-        int64_t dwi = -1;          // bitmap word being filled
+        int32_t dwi = -1;          // bitmap word being filled
         uint64_t dword = 0;
 
         while (i > 0 && j > 0) {
-            const int64_t ell = (i - 1) / BAND;
+            const int32_t ell = (i - 1) / (int32_t)BAND;
             if (ell != band) {
                 band = ell;
                 kt_hi = -1;
@@ -483,98 +490,149 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
                 }
                 wave_lds_sync();
             }
-            const int64_t t = (j - 1) + (int64_t)skew;
-            const int64_t kt = t / K;
+            const int32_t t = (j - 1) + (int32_t)skew;
+            const int32_t kt = t >> LOGK;
             if (kt > kt_hi || kt < kt_lo) {
                 // recompute tiles kt-NB+1 .. kt of this band, one lane each
                 kt_hi = kt;
-                kt_lo = kt - (int64_t)NB + 1 < 0 ? 0 : kt - (int64_t)NB + 1;
-                const uint32_t sbase = (uint32_t)kt_lo * K;
-                const uint32_t nsteps = (uint32_t)(kt_hi - kt_lo + 1) * K;
-                for (uint32_t e = lane; e < nsteps; e += 64) ystage[e] = ys[sbase + e];
+                kt_lo = kt - (int32_t)NB + 1 < 0 ? 0 : kt - (int32_t)NB + 1;
+                const uint32_t sbase = (uint32_t)kt_lo << LOGK;
+                const uint32_t nsteps = (uint32_t)(kt_hi - kt_lo + 1) << LOGK;
+                for (uint32_t e = lane; e < nsteps / 2; e += 64)
+                    ((uint32_t *)ystage)[e] =
+                        (uint32_t)ys[sbase + 2 * e] | ((uint32_t)ys[sbase + 2 * e + 1] << 16);
                 for (uint32_t e = lane; e < nsteps / 32; e += 64) {
                     const uint32_t w = (sbase >> 5) + e;
                     cbstage[e] = w < Tw ? cb[(size_t)w * 64] : 0u;
                 }
                 wave_lds_sync();
                 const uint32_t slot = (uint32_t)lane;
-                if ((int64_t)slot <= kt_hi - kt_lo) {
-                    const int64_t ktl = kt_hi - slot;
+                if ((int32_t)slot <= kt_hi - kt_lo) {
+                    const int32_t ktl = kt_hi - (int32_t)slot;
                     uint64_t V[WPL];
 #pragma unroll
                     for (int q = 0; q < WPL; ++q) V[q] = ck[((size_t)ktl * WPL + q) * 64];
-                    const uint32_t e0 = (uint32_t)(ktl - kt_lo) * K;
+                    const uint32_t e0 = (uint32_t)(ktl - kt_lo) << LOGK;
                     uint64_t *tdst = tiles + (size_t)slot * K * WPL * 2;
-#pragma unroll 4
-                    for (uint32_t o = 0; o < K; ++o) {
-                        const uint32_t e = e0 + o;
-                        const uint32_t code = (uint32_t)ystage[e] >> kShift;
-                        uint32_t carry = (cbstage[e >> 5] >> (31 - (e & 31))) & 1u;
+                    for (uint32_t o0 = 0; o0 < K; o0 += 32) {
+                        const uint32_t cw = cbstage[(e0 + o0) >> 5];
+#pragma unroll 2
+                        for (uint32_t o1 = 0; o1 < 32; o1 += 8) {
+                            // eight stream values in one 16-byte read
+                            const uint4 y8 = *(const uint4 *)(ystage + e0 + o0 + o1);
+                            const uint32_t yw[4] = {y8.x, y8.y, y8.z, y8.w};
+                            // all eight steps' match masks first: they depend on
+                            // the codes only, and reading them before any tile
+                            // write keeps each step off an LDS round trip
+                            uint64_t Mg[8][WPL];
 #pragma unroll
-                        for (int q = 0; q < WPL; ++q) {
-                            const uint64_t M = pmw[code * WPL + q];
-                            const uint64_t v = V[q];
-                            const uint64_t U = v & M;
-                            uint32_t c1, c2;
-                            const uint32_t slo =
-                                __builtin_addc((uint32_t)v, (uint32_t)U, carry, &c1);
-                            const uint32_t shi =
-                                __builtin_addc((uint32_t)(v >> 32), (uint32_t)(U >> 32), c1, &c2);
-                            carry = c2;
-                            V[q] = ((((uint64_t)shi) << 32) | slo) | (v & ~M);
-                            tdst[((size_t)o * WPL + q) * 2] = V[q];
-                            tdst[((size_t)o * WPL + q) * 2 + 1] = M;
+                            for (int k = 0; k < 8; ++k) {
+                                const uint32_t code =
+                                    ((k & 1) ? (yw[k >> 1] >> 16) : (yw[k >> 1] & 0xffffu)) >> kShift;
+#pragma unroll
+                                for (int q = 0; q < WPL; ++q) Mg[k][q] = pmw[code * WPL + q];
+                            }
+#pragma unroll
+                            for (int k = 0; k < 8; ++k) {
+                                uint32_t carry = (cw >> (31 - (o1 + k))) & 1u;
+                                uint64_t *dst = tdst + (size_t)(o0 + o1 + k) * WPL * 2;
+#pragma unroll
+                                for (int q = 0; q < WPL; ++q) {
+                                    const uint64_t M = Mg[k][q];
+                                    const uint64_t v = V[q];
+                                    const uint64_t U = v & M;
+                                    uint32_t c1, c2;
+                                    const uint32_t slo =
+                                        __builtin_addc((uint32_t)v, (uint32_t)U, carry, &c1);
+                                    const uint32_t shi = __builtin_addc(
+                                        (uint32_t)(v >> 32), (uint32_t)(U >> 32), c1, &c2);
+                                    carry = c2;
+                                    V[q] = ((((uint64_t)shi) << 32) | slo) | (v & ~M);
+                                    dst[q * 2] = V[q];
+                                    dst[q * 2 + 1] = M;
+                                }
+                            }
                         }
                     }
                 }
                 wave_lds_sync();
             }
-            // walk inside the resident tiles of this band
-            int64_t tc = t;
-            const int64_t tlo = kt_lo * K;
-            for (;;) {
-                const uint32_t slot = (uint32_t)(kt_hi - tc / K);
-                const uint32_t o = (uint32_t)(tc % K);
-                const uint64_t *col = tiles + ((size_t)slot * K + o) * WPL * 2;
-                const uint32_t rl = (uint32_t)((i - 1) - ell * BAND);
-                int q = (int)(rl / 64);
-                int b = (int)(rl % 64);
-                bool found = false;
-                uint64_t Mw = 0, cand = 0;
-                for (;;) {
-                    const uint64_t Vw = col[q * 2];
-                    Mw = col[q * 2 + 1];
-                    const uint64_t low = (b == 63) ? ~0ull : ((2ull << b) - 1);
-                    cand = (Mw | ~Vw) & low;
-                    if (cand) { found = true; break; }
-                    if (q == 0) break;
-                    --q;
-                    b = 63;
+            // walk inside the resident tiles of this band.  A window of
+            // 64/WPL columns sits in lane registers, lane l holding column
+            // (tc - l/WPL), word (l % WPL); each column then costs four
+            // readlanes and scalar arithmetic on (word q, bit b) of the row.
+            const int32_t rbase = ell * (int32_t)BAND;
+            const int32_t tfloor = kt_lo << LOGK;     // first resident step
+            int32_t tc = t;
+            int32_t q = (i - 1 - rbase) >> 6;
+            int32_t b = (i - 1 - rbase) & 63;
+            const int32_t wq0 = rbase >> 6;           // bitmap word of the band's word 0
+            bool leave = false;
+            while (!leave) {
+                const int32_t tl = tc - (int32_t)(lane / WPL);
+                uint64_t VL = 0, ML = 0;
+                if (tl >= tfloor) {
+                    const uint32_t sl = (uint32_t)(kt_hi - (tl >> LOGK));
+                    const uint64_t *e =
+                        tiles + (((size_t)sl << LOGK) + ((uint32_t)tl & (K - 1))) * WPL * 2 +
+                        (lane % WPL) * 2;
+                    VL = e[0];
+                    ML = e[1];
                 }
-                if (!found) {  // up through the rest of the band in column j
-                    i = ell * BAND;
-                    break;
+                if (wq0 + q != dwi) {
+                    if (dwi >= 0 && dword && lane == 0) dg[dwi] = dword;
+                    dwi = wq0 + q;
+                    dword = 0;
                 }
-                const int r = 63 - __builtin_clzll(cand);
-                const int64_t row = ell * BAND + (int64_t)q * 64 + r + 1;
-                if ((Mw >> r) & 1ull) {
-                    const int64_t w = (row - 1) >> 6;
-                    if (w != dwi) {
-                        if (dwi >= 0 && dword && lane == 0) dg[dwi] = dword;
-                        dwi = w;
-                        dword = 0;
+                const int32_t avail = tc - tfloor + 1;    // columns resident from tc down
+                int32_t kmax = avail < (int32_t)(64 / WPL) ? avail : (int32_t)(64 / WPL);
+                kmax = kmax < j ? kmax : j;
+                int32_t k = 0;
+                for (; k < kmax; ++k) {
+                    int32_t idx = k * WPL + q;
+                    uint64_t Vw = readlane64(VL, idx), Mw = readlane64(ML, idx);
+                    uint64_t cand = (Mw | ~Vw) & (~0ull >> (63 - b));
+                    if (__builtin_expect(cand == 0, 0)) {
+                        // up through the rest of word q: continue in the words below
+                        while (cand == 0 && q > 0) {
+                            if (dword && lane == 0) dg[dwi] = dword;
+                            --q;
+                            --idx;
+                            --dwi;
+                            dword = 0;
+                            b = 63;
+                            Vw = readlane64(VL, idx);
+                            Mw = readlane64(ML, idx);
+                            cand = Mw | ~Vw;
+                        }
+                        if (cand == 0) {  // left the band upward in this column
+                            b = -1;
+                            leave = true;
+                            break;
+                        }
                     }
-                    dword |= 1ull << ((row - 1) & 63);
-                    i = row - 1;
-                } else {
-                    i = row;
+                    const int32_t r = 63 - (int32_t)__builtin_clzll(cand);
+                    const uint32_t d = (uint32_t)(Mw >> r) & 1u;
+                    dword |= (uint64_t)d << r;
+                    b = r - (int32_t)d;
+                    if (__builtin_expect(b < 0, 0)) {
+                        if (q == 0) {     // diagonal step out of the band
+                            ++k;
+                            leave = true;
+                            break;
+                        }
+                        if (dword && lane == 0) dg[dwi] = dword;
+                        --q;
+                        --dwi;
+                        dword = 0;
+                        b = 63;
+                    }
                 }
-                --j;
-                --tc;
-                if (i == 0 || j == 0) break;
-                if ((i - 1) / BAND != ell) break;
-                if (tc < tlo) break;
+                j -= k;
+                tc -= k;
+                if (j == 0 || tc < tfloor) leave = true;
             }
+            i = rbase + q * 64 + b + 1;
         }
         if (dwi >= 0 && dword && lane == 0) dg[dwi] = dword;
     }
@@ -627,25 +685,36 @@ hipError_t launch_emit(const EmitArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-const void *tb_symbol(int wpl) {
+#define LCS_TB_SYM(W)                                              \
+    (logk == 6 ? (const void *)&k_traceback<W, 6>                  \
+               : logk == 7 ? (const void *)&k_traceback<W, 7>      \
+                           : (const void *)&k_traceback<W, 8>)
+const void *tb_symbol(int wpl, int ckpt_every) {
+    const int logk = ckpt_every == 64 ? 6 : ckpt_every == 128 ? 7 : 8;
     switch (wpl) {
-        case 1: return (const void *)&k_traceback<1>;
-        case 2: return (const void *)&k_traceback<2>;
-        case 4: return (const void *)&k_traceback<4>;
-        default: return (const void *)&k_traceback<8>;
+        case 1: return LCS_TB_SYM(1);
+        case 2: return LCS_TB_SYM(2);
+        case 4: return LCS_TB_SYM(4);
+        default: return LCS_TB_SYM(8);
     }
 }
+#undef LCS_TB_SYM
 
 hipError_t launch_tb(int wpl, const TbArgs &a, uint32_t grid, hipStream_t s) {
+    if (a.ckpt_every != 64 && a.ckpt_every != 128 && a.ckpt_every != 256) return hipErrorInvalidValue;
     const size_t lds = tb_lds_bytes(wpl, a.sigma, a.ckpt_every, a.nb);
-    switch (wpl) {
-        case 1: hipLaunchKernelGGL((k_traceback<1>), dim3(grid), dim3(kTbBlock), lds, s, a); break;
-        case 2: hipLaunchKernelGGL((k_traceback<2>), dim3(grid), dim3(kTbBlock), lds, s, a); break;
-        case 4: hipLaunchKernelGGL((k_traceback<4>), dim3(grid), dim3(kTbBlock), lds, s, a); break;
-        case 8: hipLaunchKernelGGL((k_traceback<8>), dim3(grid), dim3(kTbBlock), lds, s, a); break;
-        default: return hipErrorInvalidValue;
+    const int logk = a.ckpt_every == 64 ? 6 : a.ckpt_every == 128 ? 7 : 8;
+#define LCS_TB_LAUNCH(W, L)                                                               \
+    if (wpl == W && logk == L) {                                                          \
+        hipLaunchKernelGGL((k_traceback<W, L>), dim3(grid), dim3(kTbBlock), lds, s, a); \
+        return hipGetLastError();                                                         \
     }
-    return hipGetLastError();
+    LCS_TB_LAUNCH(1, 6) LCS_TB_LAUNCH(1, 7) LCS_TB_LAUNCH(1, 8)
+    LCS_TB_LAUNCH(2, 6) LCS_TB_LAUNCH(2, 7) LCS_TB_LAUNCH(2, 8)
+    LCS_TB_LAUNCH(4, 6) LCS_TB_LAUNCH(4, 7) LCS_TB_LAUNCH(4, 8)
+    LCS_TB_LAUNCH(8, 6) LCS_TB_LAUNCH(8, 7) LCS_TB_LAUNCH(8, 8)
+#undef LCS_TB_LAUNCH
+    return hipErrorInvalidValue;
 }
 
 }  // namespace lcs

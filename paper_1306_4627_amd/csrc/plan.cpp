@@ -38,8 +38,8 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
     out.cfg = cfg;
     if (cfg.wpl != 0 && cfg.wpl != 1 && cfg.wpl != 2 && cfg.wpl != 4 && cfg.wpl != 8)
         return "words_per_lane must be 1, 2, 4 or 8";
-    if (cfg.traceback && (cfg.ckpt <= 0 || cfg.ckpt % kChunk != 0))
-        return "ckpt_interval must be a positive multiple of 64";
+    if (cfg.traceback && cfg.ckpt != 64 && cfg.ckpt != 128 && cfg.ckpt != 256)
+        return "ckpt_interval must be 64, 128 or 256";
     const size_t np = pairs.size();
     out.pair_class.assign(np, UINT32_MAX);
 
