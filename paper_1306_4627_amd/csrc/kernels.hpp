@@ -54,6 +54,7 @@ struct FillArgs {
     uint32_t *error;           // set to 1 when a bounded wait runs out
     uint32_t item_begin;
     uint32_t item_end;
+    uint32_t prio_T;           // items with at least this many steps run at raised priority
     uint32_t spin_limit;       // polls before a wait gives up
     int32_t sigma;             // code sigma is the zero-mask sentinel
     int32_t ckpt_every;        // steps between checkpoints (traceback only)
@@ -85,6 +86,7 @@ struct TbArgs {
     int32_t sigma;
     int32_t ckpt_every;
     int32_t nb;                 // tiles recomputed together (one per lane)
+    uint32_t prio_n;            // pairs with at least this many columns walk at raised priority
 };
 
 // Emit: bitmap of diagonal rows -> LCS bytes (X symbols in row order).

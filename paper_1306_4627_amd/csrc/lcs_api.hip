@@ -50,6 +50,8 @@ struct ClassDev {
     uint32_t *q_fill = nullptr, *q_tb = nullptr;
     uint32_t fill_grid = 1, tb_grid = 1;
     int nb = 1;                        // traceback tiles recomputed together
+    uint32_t prio_T = 0xffffffffu;     // fill items this long run at raised priority
+    uint32_t prio_n = 0xffffffffu;     // walks this long run at raised priority
     // plain mode: one launch per pair
     std::vector<uint32_t> pl_pair;     // pair of each launch
     std::vector<uint32_t> pl_begin, pl_end, pl_tb;  // item range, index in tb list
@@ -544,6 +546,14 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         D.fill_grid = resident_grid(ctx, fill_symbol(C.wpl, cfg.traceback),
                                     fill_lds_bytes(C.wpl, sigma), (D.nitems + 3) / 4,
                                     cap > 0 ? (cap + 3) / 4 : 0);
+        // raised priority for the items and walks within half of the longest
+        {
+            uint32_t mt = 0, mn = 0;
+            for (uint32_t T : C.it_T) mt = std::max(mt, T);
+            for (uint32_t pr : C.tb_pair) mn = std::max<uint32_t>(mn, (uint32_t)pairs[pr].n);
+            D.prio_T = std::max<uint32_t>(mt / 2, 1);
+            D.prio_n = std::max<uint32_t>(mn / 2, 1);
+        }
         // tiles per recompute batch: as many as fit 32 KiB of LDS per wave
         {
             const size_t tile = (size_t)cfg.ckpt * C.wpl * 16;
@@ -633,6 +643,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         fa.error = b->error;
         fa.item_begin = 0;
         fa.item_end = D.nitems;
+        fa.prio_T = D.prio_T;
         fa.spin_limit = b->spin_limit;
         fa.sigma = b->sigma;
         fa.ckpt_every = b->ckpt;
@@ -663,6 +674,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         ta.sigma = b->sigma;
         ta.ckpt_every = b->ckpt;
         ta.nb = D.nb;
+        ta.prio_n = D.prio_n;
         return ta;
     };
     EmitArgs ea{};

@@ -149,6 +149,10 @@ __device__ __forceinline__ void load16(const uint16_t *ys, uint32_t t0, uint32_t
     for (int e = 0; e < 8; ++e) d[e] = (uint32_t)p[2 * e] | ((uint32_t)p[2 * e + 1] << 16);
 }
 
+#ifndef LCS_FILL_HOIST
+#define LCS_FILL_HOIST 8
+#endif
+
 // Sixteen column steps t..t+15 of one lane.  The carry-in lane mask of a
 // step is the carry-out mask of the previous step shifted up by one lane,
 // with segment starts cleared; with CHAIN, lane 0 takes the hand-over bit of
@@ -160,34 +164,45 @@ __device__ __forceinline__ void run16(const uint32_t (&Yg)[8], uint32_t t, const
                                       uint64_t notstart, uint64_t &cmask, uint32_t &acc,
                                       uint32_t *cbp, uint32_t (&vlo)[WPL], uint32_t (&vhi)[WPL],
                                       uint64_t &inbits, uint64_t &outbits) {
+    constexpr int H = LCS_FILL_HOIST;   // steps whose match masks are read together
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const uint32_t off = (e & 1) ? (Yg[e >> 1] >> 16) : (Yg[e >> 1] & 0xffffu);
-        const char *row = lanecol + off;
-        uint64_t M[WPL];
+    for (int h = 0; h < 16 / H; ++h) {
+        // the match masks of H steps are read up front: they depend on the
+        // stream only, so their LDS latency overlaps the column steps
+        uint64_t Mg[H][WPL];
 #pragma unroll
-        for (int q = 0; q < WPL; ++q) M[q] = *(const uint64_t *)(row + q * 512);
-        uint64_t cm = cmask;
-        if (CHAIN) {
-            cm |= inbits & 1ull;
-            inbits >>= 1;
+        for (int e = 0; e < H; ++e) {
+            const int s = h * H + e;
+            const uint32_t y2 = Yg[s >> 1];
+            const uint32_t off = (s & 1) ? (y2 >> 16) : (y2 & 0xffffu);
+            const char *row = lanecol + off;
+#pragma unroll
+            for (int q = 0; q < WPL; ++q) Mg[e][q] = *(const uint64_t *)(row + q * 512);
         }
-        if (TB) {
-            uint32_t cj;
-            acc = __builtin_addc(acc, acc, (uint32_t)__builtin_amdgcn_inverse_ballot_w64(cm), &cj);
-            if (e == 15 && (t & 16u)) cbp[(size_t)((t + e) >> 5) * 64] = acc;
+#pragma unroll
+        for (int e = 0; e < H; ++e) {
+            uint64_t cm = cmask;
+            if (CHAIN) {
+                cm |= inbits & 1ull;
+                inbits >>= 1;
+            }
+            if (TB) {
+                uint32_t cj;
+                acc = __builtin_addc(acc, acc, (uint32_t)__builtin_amdgcn_inverse_ballot_w64(cm), &cj);
+                if (h * H + e == 15 && (t & 16u)) cbp[(size_t)((t + 15) >> 5) * 64] = acc;
+            }
+            column_step<WPL>(vlo, vhi, Mg[e], cm);
+            if (CHAIN) {
+                outbits = (outbits >> 1) | (cm & 0x8000000000000000ull);
+                // pin the accumulation to this step: sunk to its single use,
+                // it would keep every step's carry mask alive until the chunk end
+                asm volatile("" : "+s"(outbits), "+s"(inbits));
+            }
+            cmask = (cm << 1) & notstart;
         }
-        column_step<WPL>(vlo, vhi, M, cm);
-        if (CHAIN) {
-            outbits = (outbits >> 1) | (cm & 0x8000000000000000ull);
-            // pin the accumulation to this step: sunk to its single use,
-            // it would keep every step's carry mask alive until the chunk end
-            asm volatile("" : "+s"(outbits), "+s"(inbits));
-        }
-        cmask = (cm << 1) & notstart;
         // keep the scheduler from spreading the scalar work of many steps
         // across each other (it would hold dozens of masks live)
-        if ((e & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -281,6 +296,10 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
         load16(ys, 0, Y0);
         load16(ys, 16, Y1);
         const bool chain = prev >= 0 || feeds;
+        // The longest items bound the kernel's duration: let the SIMD issue
+        // their instructions first; shorter items fill the remaining slots.
+        if (T >= a.prio_T) __builtin_amdgcn_s_setprio(2);
+        else __builtin_amdgcn_s_setprio(0);
         uint64_t pw0 = 0, pw1 = 0;   // hand-over words requested one group early
 
         for (uint32_t c = 0; c < nch; ++c) {
@@ -453,6 +472,9 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
         const uint32_t n = a.pair_n[p];
         const uint8_t *xc = a.xcodes + a.pair_xoff[p];
         uint64_t *dg = a.diag + a.pair_diag[p];
+        // the longest walks bound the kernel's duration (see k_fill)
+        if (n >= a.prio_n) __builtin_amdgcn_s_setprio(2);
+        else __builtin_amdgcn_s_setprio(0);
 
         int32_t i = (int32_t)m, j = (int32_t)n;
         int32_t band = -1, kt_hi = -1, kt_lo = 0;

@@ -27,8 +27,18 @@ bool wpl_fits(int sigma, int wpl) {
     return sigma * wpl <= 127 && (size_t)4 * (sigma + 1) * wpl * 512 <= 160 * 1024;
 }
 
-static int auto_wpl(uint64_t W, int sigma) {
-    int w = W <= 8 ? 1 : (W <= 32 ? 2 : 4);
+// One words-per-lane for the whole batch (one fill launch): two words per
+// lane once most of the cells belong to pairs longer than 16 words (the
+// per-step overhead is then spread over 128 rows), one word otherwise
+// (short columns keep more lanes busy).
+static int auto_batch_wpl(const std::vector<PairShape> &pairs, int sigma) {
+    double big = 0, all = 0;
+    for (const PairShape &p : pairs) {
+        const double c = (double)p.m * (double)p.n;
+        all += c;
+        if ((p.m + 63) / 64 > 16) big += c;
+    }
+    int w = (all > 0 && big >= 0.5 * all) ? 2 : 1;
     int mw = max_wpl(sigma);
     return w < mw ? w : mw;
 }
@@ -43,6 +53,7 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
     const size_t np = pairs.size();
     out.pair_class.assign(np, UINT32_MAX);
 
+    const int batch_wpl = cfg.wpl ? cfg.wpl : auto_batch_wpl(pairs, cfg.sigma);
     // assign pairs to classes by words-per-lane
     int class_of_wpl[9];
     for (int &c : class_of_wpl) c = -1;
@@ -51,8 +62,9 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
         const PairShape &p = pairs[k];
         out.cells += p.m * p.n;
         if (p.m == 0 || p.n == 0) continue;
-        uint64_t W = ceil_div(p.m, 64);
-        int wpl = cfg.wpl ? cfg.wpl : auto_wpl(W, cfg.sigma);
+        int wpl = batch_wpl;
+        // a pair too long for the batch's width takes a wider one
+        while (wpl < 8 && p.m > max_rows(wpl)) wpl *= 2;
         if (wpl == 0 || !wpl_fits(cfg.sigma, wpl)) return "alphabet too large for words_per_lane";
         if (p.m > max_rows(wpl)) return "sequence X longer than the supported row count";
         if (p.n > 0x7fffffffull) return "sequence Y too long";
