@@ -61,6 +61,24 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def measured_traffic(workload: str):
+    """HBM bytes per fill launch from the committed rocprofv3 counter runs,
+    or None when they were taken on a different kernel source or workload."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1306_4627_amd", "csrc", "lcs_kernels.hip")
+    rec_file = os.path.join(ROOT, "profiles", "k_fill_batch_related_4096.md")
+    try:
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        for line in open(rec_file):
+            if line.startswith("traffic-record:"):
+                rec = json.loads(line.split(":", 1)[1])
+                if rec["source_sha256_prefix"] == h and rec["workload"] == workload:
+                    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
 def cpu_baseline(pairs, traceback: bool, budget_cells: float, threads: int):
     """Time the oracle on a random sample of the workload's pairs."""
     import oracle
@@ -105,7 +123,19 @@ def main() -> int:
     ap.add_argument("--cpu-cells", type=float, default=6e9)
     ap.add_argument("--wpl", type=int, default=0)
     ap.add_argument("--ckpt", type=int, default=0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device-to-device copy of BYTES bytes (the "
+                         "reference for scaling HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(args.calibrate_copy, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": args.calibrate_copy}), flush=True)
+        return 0
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the workload is the one-GPU "
               "share); --gpus must be 1", file=sys.stderr)
@@ -153,7 +183,8 @@ def main() -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": config,
         "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_TCUPS, 1),
-                     "unit": "TCUPS", "frac": round(achieved / PEAK_TCUPS, 4), "traffic": None,
+                     "unit": "TCUPS", "frac": round(achieved / PEAK_TCUPS, 4),
+                     "traffic": measured_traffic(config["workload"]),
                      "kernel": "k_fill", "fill_ms": round(fill_avg, 4),
                      "eager_pass_ms": round(float(np.mean(eager_ms)), 4)},
         "plan": {k: info[k] for k in ("groups", "lanes", "lane_steps", "words_per_lane",
