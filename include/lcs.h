@@ -89,12 +89,21 @@ typedef struct lcs_batch lcs_batch;
  *                    traceback (64, 128 or 256);
  *  persistent_waves: cap on resident work-groups of the persistent kernels;
  *  plain           : 1 = no packing: one pair per work-group and one launch
- *                    per pair (the plain per-pair path, for comparison). */
+ *                    per pair (the plain per-pair path, for comparison);
+ *  strip_rows      : rows per traceback strip (rounded up to a multiple of
+ *                    64*words_per_lane; default 2048).  The walk of a pair is
+ *                    split into strips walked in parallel from estimated
+ *                    entry columns and then reconciled; the result does not
+ *                    depend on this value;
+ *  tb_tiles        : checkpoint intervals of one band the traceback
+ *                    recomputes at once (1..8, default 2). */
 typedef struct {
     int32_t words_per_lane;
     int32_t ckpt_interval;
     int32_t persistent_waves;
     int32_t plain;
+    int32_t strip_rows;
+    int32_t tb_tiles;
 } lcs_tuning;
 
 /* What a batch was planned into (filled by lcs_batch_info). */

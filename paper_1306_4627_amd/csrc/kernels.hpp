@@ -60,9 +60,9 @@ struct FillArgs {
     int32_t ckpt_every;        // steps between checkpoints (traceback only)
 };
 
-// Traceback walk: one wave per pair, persistent.  The walk records the rows
-// where it takes a diagonal step in a per-pair bitmap over X (bit r of word
-// w stands for row 64*w + r + 1); k_emit turns the bitmap into bytes.
+// Traceback walk: one wave per ticket, persistent.  The walk records the
+// rows where it takes a diagonal step in a per-pair bitmap over X (bit r of
+// word w stands for row 64*w + r + 1); k_emit turns the bitmap into bytes.
 struct TbArgs {
     const uint8_t *xcodes;
     const uint64_t *pair_xoff;
@@ -78,16 +78,29 @@ struct TbArgs {
     const uint64_t *ln_ys;
     const uint64_t *ckpt;
     const uint32_t *cbits;
-    const uint32_t *tb_pair;
-    const uint32_t *tb_item;
-    const uint32_t *tb_lane0;
-    uint32_t ntb;
+    const uint32_t *tb_pair;    // per traceback entry: pair
+    const uint32_t *tb_item;    //   item holding its first lane
+    const uint32_t *tb_lane0;   //   lane of that item
+    const uint32_t *tb_band0;   //   first entry of its band crossings
+    const uint32_t *tb_strip0;  //   first entry of its strip results
+    const uint32_t *tk_t;       // per ticket: traceback entry
+    const uint32_t *tk_s;       // per ticket: strip (speculative and fix-up passes)
+    uint32_t nticket;
     uint32_t *queue;
+    uint32_t *cross;            // per band: column where the speculative walk leaves it
+    uint32_t *strip_res;        // per strip: {entry column of the fix-up, exit column}
+    uint32_t strip_bands;       // bands per strip
+    int32_t mode;               // kTbSpec, kTbFix or kTbSeal
     int32_t sigma;
     int32_t ckpt_every;
     int32_t nb;                 // tiles recomputed together (one per lane)
-    uint32_t prio_n;            // pairs with at least this many columns walk at raised priority
 };
+
+// Traceback passes over strips (runs of bands of one pair): speculative
+// walks from estimated entry columns, fix-up walks from the speculative exit
+// of the strip above until they rejoin the speculative path, and one
+// sequential seal per pair.
+enum : int32_t { kTbSpec = 0, kTbFix = 1, kTbSeal = 2 };
 
 // Emit: bitmap of diagonal rows -> LCS bytes (X symbols in row order).
 struct EmitArgs {

@@ -43,19 +43,27 @@ struct ClassDev {
     uint32_t *ln_word0 = nullptr, *ln_skew = nullptr;
     uint64_t *ln_ys = nullptr;
     uint32_t *tb_pair = nullptr, *tb_item = nullptr, *tb_lane0 = nullptr;
+    uint32_t *tb_band0 = nullptr, *tb_strip0 = nullptr;
+    uint32_t *sp_t = nullptr, *sp_s = nullptr, *fx_t = nullptr, *fx_s = nullptr, *sl_t = nullptr;
+    uint32_t nsp = 0, nfx = 0, nsl = 0, strip_bands = 1;
+    uint32_t *cross = nullptr, *strip_res = nullptr;
     uint64_t *ckpt = nullptr;
     uint32_t *cbits = nullptr;
     uint64_t *xfer = nullptr;
-    uint32_t *plain_ctr = nullptr;     // plain mode: two queue counters per pair
-    uint32_t *q_fill = nullptr, *q_tb = nullptr;
-    uint32_t fill_grid = 1, tb_grid = 1;
+    uint32_t *plain_ctr = nullptr;     // plain mode: kQueues queue counters per pair
+    uint32_t *q_fill = nullptr, *q_spec = nullptr, *q_fix = nullptr, *q_seal = nullptr;
+    uint32_t fill_grid = 1, sp_grid = 1, fx_grid = 1, sl_grid = 1;
     int nb = 1;                        // traceback tiles recomputed together
     uint32_t prio_T = 0xffffffffu;     // fill items this long run at raised priority
-    uint32_t prio_n = 0xffffffffu;     // walks this long run at raised priority
-    // plain mode: one launch per pair
+    // plain mode: one launch per pair and pass
     std::vector<uint32_t> pl_pair;     // pair of each launch
     std::vector<uint32_t> pl_begin, pl_end, pl_tb;  // item range, index in tb list
+    std::vector<uint32_t> pl_sp, pl_nsp, pl_fx, pl_nfx, pl_sl;  // ticket ranges (pl_sl: -1 = none)
 };
+
+// queue counters per class (and per pair in plain mode): fill, speculative,
+// fix-up and seal passes
+constexpr int kQueues = 4;
 
 // Bump allocator over one device allocation.
 struct Carver {
@@ -181,6 +189,7 @@ static lcs_status check_tuning(const lcs_tuning *t) {
         t->ckpt_interval != 256)
         return LCS_ERR_ARG;
     if (t->persistent_waves < 0 || t->plain < 0 || t->plain > 1) return LCS_ERR_ARG;
+    if (t->strip_rows < 0 || t->tb_tiles < 0 || t->tb_tiles > 8) return LCS_ERR_ARG;
     return LCS_OK;
 }
 
@@ -190,6 +199,7 @@ static void fill_plan_config(PlanConfig &cfg, int sigma, uint32_t flags, const l
     cfg.ckpt = (t && t->ckpt_interval) ? t->ckpt_interval : 128;
     cfg.sigma = sigma;
     cfg.plain = t && t->plain;
+    cfg.strip_rows = (t && t->strip_rows) ? t->strip_rows : 2048;
 }
 
 static void stats_from_plan(const Plan &p, uint64_t npairs, lcs_batch_stats *out) {
@@ -236,22 +246,35 @@ extern "C" const char *lcs_last_error(void) { return g_last_error; }
 extern "C" lcs_status lcs_create(lcs_ctx **out, int device, size_t mem_budget_bytes) {
     if (!out) return LCS_ERR_ARG;
     int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return LCS_ERR_DEVICE;
-    if (device < 0 || device >= count) return LCS_ERR_DEVICE;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) {
+        note_error("hipGetDeviceCount", e);
+        return LCS_ERR_DEVICE;
+    }
+    if (device < 0 || device >= count) {
+        std::snprintf(g_last_error, sizeof g_last_error, "device %d out of range (%d visible)",
+                      device, count);
+        return LCS_ERR_DEVICE;
+    }
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return LCS_ERR_DEVICE;
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LCS_ERR_DEVICE;
-    if (hipSetDevice(device) != hipSuccess) return LCS_ERR_DEVICE;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        std::snprintf(g_last_error, sizeof g_last_error, "device %d is %s, not gfx950", device,
+                      prop.gcnArchName);
+        return LCS_ERR_DEVICE;
+    }
+    HIP_TRY(hipSetDevice(device));
     std::unique_ptr<lcs_ctx> c(new (std::nothrow) lcs_ctx());
     if (!c) return LCS_ERR_NOMEM;
     c->device = device;
     c->num_cus = prop.multiProcessorCount;
     c->arch = prop.gcnArchName;
-    if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess)
-        return LCS_ERR_DEVICE;
+    HIP_TRY(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
     c->stream = c->own_stream;
     size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    e = hipMemGetInfo(&fr, &tot);
+    if (e != hipSuccess) {
+        note_error("hipMemGetInfo", e);
         (void)hipStreamDestroy(c->own_stream);
         return LCS_ERR_DEVICE;
     }
@@ -332,8 +355,8 @@ static size_t carve(lcs_batch *b, char *base) {
     uint64_t nz = 1;
     for (size_t ci = 0; ci < p.classes.size(); ++ci) {
         const ClassPlan &C = p.classes[ci];
-        nz += 2;
-        if (b->plain) nz += 2 * C.tb_pair.size();
+        nz += kQueues;
+        if (b->plain) nz += kQueues * C.tb_pair.size();
     }
     b->zero = cv.take<uint32_t>(nz);
     b->nzero = nz;
@@ -366,15 +389,30 @@ static size_t carve(lcs_batch *b, char *base) {
         D.tb_pair = cv.take<uint32_t>(D.ntb + 1);
         D.tb_item = cv.take<uint32_t>(D.ntb + 1);
         D.tb_lane0 = cv.take<uint32_t>(D.ntb + 1);
+        D.tb_band0 = cv.take<uint32_t>(C.tb_band0.size() + 1);
+        D.tb_strip0 = cv.take<uint32_t>(C.tb_strip0.size() + 1);
+        D.nsp = (uint32_t)C.sp_t.size();
+        D.nfx = (uint32_t)C.fx_t.size();
+        D.nsl = (uint32_t)C.sl_t.size();
+        D.strip_bands = C.strip_bands;
+        D.sp_t = cv.take<uint32_t>(D.nsp + 1);
+        D.sp_s = cv.take<uint32_t>(D.nsp + 1);
+        D.fx_t = cv.take<uint32_t>(D.nfx + 1);
+        D.fx_s = cv.take<uint32_t>(D.nfx + 1);
+        D.sl_t = cv.take<uint32_t>(D.nsl + 1);
+        D.cross = cv.take<uint32_t>(C.n_bands + 1);
+        D.strip_res = cv.take<uint32_t>(2 * C.n_strips + 2);
         D.ckpt = cv.take<uint64_t>(C.ck_words + 1);
         D.cbits = cv.take<uint32_t>(C.cb_words + 1);
         D.xfer = b->zero64 ? b->zero64 + z64 : nullptr;
         z64 += C.xf_words;
         D.q_fill = b->zero ? b->zero + zc : nullptr;
-        D.q_tb = b->zero ? b->zero + zc + 1 : nullptr;
-        zc += 2;
+        D.q_spec = b->zero ? b->zero + zc + 1 : nullptr;
+        D.q_fix = b->zero ? b->zero + zc + 2 : nullptr;
+        D.q_seal = b->zero ? b->zero + zc + 3 : nullptr;
+        zc += kQueues;
         D.plain_ctr = b->zero ? b->zero + zc : nullptr;
-        if (b->plain) zc += 2 * D.ntb;
+        if (b->plain) zc += kQueues * D.ntb;
     }
     return cv.off + 256;
 }
@@ -542,28 +580,39 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         UP(D.tb_pair, C.tb_pair.data(), C.tb_pair.size() * 4);
         UP(D.tb_item, C.tb_item.data(), C.tb_item.size() * 4);
         UP(D.tb_lane0, C.tb_lane0.data(), C.tb_lane0.size() * 4);
+        UP(D.tb_band0, C.tb_band0.data(), C.tb_band0.size() * 4);
+        UP(D.tb_strip0, C.tb_strip0.data(), C.tb_strip0.size() * 4);
+        UP(D.sp_t, C.sp_t.data(), C.sp_t.size() * 4);
+        UP(D.sp_s, C.sp_s.data(), C.sp_s.size() * 4);
+        UP(D.fx_t, C.fx_t.data(), C.fx_t.size() * 4);
+        UP(D.fx_s, C.fx_s.data(), C.fx_s.size() * 4);
+        UP(D.sl_t, C.sl_t.data(), C.sl_t.size() * 4);
         const int cap = tuning ? tuning->persistent_waves : 0;
         D.fill_grid = resident_grid(ctx, fill_symbol(C.wpl, cfg.traceback),
                                     fill_lds_bytes(C.wpl, sigma), (D.nitems + 3) / 4,
                                     cap > 0 ? (cap + 3) / 4 : 0);
-        // raised priority for the items and walks within half of the longest
+        // raised priority for the items within half of the longest
         {
-            uint32_t mt = 0, mn = 0;
+            uint32_t mt = 0;
             for (uint32_t T : C.it_T) mt = std::max(mt, T);
-            for (uint32_t pr : C.tb_pair) mn = std::max<uint32_t>(mn, (uint32_t)pairs[pr].n);
             D.prio_T = std::max<uint32_t>(mt / 2, 1);
-            D.prio_n = std::max<uint32_t>(mn / 2, 1);
         }
-        // tiles per recompute batch: as many as fit 32 KiB of LDS per wave
+        D.nb = (tuning && tuning->tb_tiles) ? tuning->tb_tiles : 2;
         {
-            const size_t tile = (size_t)cfg.ckpt * C.wpl * 16;
-            int nb = (int)((32 * 1024 - 2048) / tile);
-            D.nb = nb < 1 ? 1 : (nb > 8 ? 8 : nb);
+            const void *sym = tb_symbol(C.wpl, cfg.ckpt);
+            const size_t lds = tb_lds_bytes(C.wpl, sigma, cfg.ckpt, D.nb);
+            D.sp_grid = resident_grid(ctx, sym, lds, (D.nsp + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
+            D.fx_grid = resident_grid(ctx, sym, lds, (D.nfx + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
+            D.sl_grid = resident_grid(ctx, sym, lds, (D.nsl + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
         }
-        D.tb_grid = resident_grid(ctx, tb_symbol(C.wpl, cfg.ckpt), tb_lds_bytes(C.wpl, sigma, cfg.ckpt, D.nb),
-                                  (D.ntb + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
         if (bp->plain) {
-            // one launch per pair: items of a pair are consecutive
+            // one launch per pair: items of a pair are consecutive, and so
+            // are the tickets of one traceback entry in each pass
+            std::vector<uint32_t> sp_first(D.ntb + 1, D.nsp), fx_first(D.ntb + 1, D.nfx),
+                sl_of(D.ntb, 0xffffffffu);
+            for (uint32_t k = D.nsp; k-- > 0;) sp_first[C.sp_t[k]] = k;
+            for (uint32_t k = D.nfx; k-- > 0;) fx_first[C.fx_t[k]] = k;
+            for (uint32_t k = 0; k < D.nsl; ++k) sl_of[C.sl_t[k]] = k;
             for (uint32_t t = 0; t < D.ntb; ++t) {
                 const uint32_t pr = C.tb_pair[t];
                 uint32_t first = C.tb_item[t], last = first;
@@ -572,6 +621,14 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
                 D.pl_begin.push_back(first);
                 D.pl_end.push_back(last + 1);
                 D.pl_tb.push_back(t);
+                uint32_t nsp = 0, nfx = 0;
+                for (uint32_t k = sp_first[t]; k < D.nsp && C.sp_t[k] == t; ++k) ++nsp;
+                for (uint32_t k = fx_first[t]; k < D.nfx && C.fx_t[k] == t; ++k) ++nfx;
+                D.pl_sp.push_back(sp_first[t]);
+                D.pl_nsp.push_back(nsp);
+                D.pl_fx.push_back(fx_first[t]);
+                D.pl_nfx.push_back(nfx);
+                D.pl_sl.push_back(sl_of[t]);
             }
         }
     }
@@ -649,7 +706,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         fa.ckpt_every = b->ckpt;
         return fa;
     };
-    auto tb_args = [&](size_t ci) {
+    auto tb_args = [&](size_t ci, int32_t mode) {
         const ClassDev &D = b->cls[ci];
         TbArgs ta{};
         ta.xcodes = b->xcodes;
@@ -669,12 +726,31 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         ta.tb_pair = D.tb_pair;
         ta.tb_item = D.tb_item;
         ta.tb_lane0 = D.tb_lane0;
-        ta.ntb = D.ntb;
-        ta.queue = D.q_tb;
+        ta.tb_band0 = D.tb_band0;
+        ta.tb_strip0 = D.tb_strip0;
+        ta.cross = D.cross;
+        ta.strip_res = D.strip_res;
+        ta.strip_bands = D.strip_bands;
         ta.sigma = b->sigma;
         ta.ckpt_every = b->ckpt;
         ta.nb = D.nb;
-        ta.prio_n = D.prio_n;
+        ta.mode = mode;
+        if (mode == kTbSpec) {
+            ta.tk_t = D.sp_t;
+            ta.tk_s = D.sp_s;
+            ta.nticket = D.nsp;
+            ta.queue = D.q_spec;
+        } else if (mode == kTbFix) {
+            ta.tk_t = D.fx_t;
+            ta.tk_s = D.fx_s;
+            ta.nticket = D.nfx;
+            ta.queue = D.q_fix;
+        } else {
+            ta.tk_t = D.sl_t;
+            ta.tk_s = D.sl_t;      // unused by the seal pass
+            ta.nticket = D.nsl;
+            ta.queue = D.q_seal;
+        }
         return ta;
     };
     EmitArgs ea{};
@@ -700,7 +776,9 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
             for (size_t ci = 0; ci < b->cls.size(); ++ci) {
                 const ClassDev &D = b->cls[ci];
                 if (!D.ntb) continue;
-                HIP_TRY(launch_tb(D.wpl, tb_args(ci), D.tb_grid, s));
+                HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbSpec), D.sp_grid, s));
+                if (D.nfx) HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbFix), D.fx_grid, s));
+                if (D.nsl) HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbSeal), D.sl_grid, s));
             }
             HIP_TRY(launch_emit(ea, s));
         }
@@ -714,17 +792,32 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
                 FillArgs fa = fill_args(ci);
                 fa.item_begin = D.pl_begin[k];
                 fa.item_end = D.pl_end[k];
-                fa.queue = ctr + 2 * k;
+                fa.queue = ctr + kQueues * k;
                 uint32_t g = (fa.item_end - fa.item_begin + 3) / 4;
                 HIP_TRY(launch_fill(D.wpl, tb, fa, g, s));
                 if (tb) {
-                    TbArgs ta = tb_args(ci);
-                    ta.tb_pair = D.tb_pair + D.pl_tb[k];
-                    ta.tb_item = D.tb_item + D.pl_tb[k];
-                    ta.tb_lane0 = D.tb_lane0 + D.pl_tb[k];
-                    ta.ntb = 1;
-                    ta.queue = ctr + 2 * k + 1;
-                    HIP_TRY(launch_tb(D.wpl, ta, 1, s));
+                    TbArgs ta = tb_args(ci, kTbSpec);
+                    ta.tk_t += D.pl_sp[k];
+                    ta.tk_s += D.pl_sp[k];
+                    ta.nticket = D.pl_nsp[k];
+                    ta.queue = ctr + kQueues * k + 1;
+                    HIP_TRY(launch_tb(D.wpl, ta, (ta.nticket + 3) / 4, s));
+                    if (D.pl_nfx[k]) {
+                        ta = tb_args(ci, kTbFix);
+                        ta.tk_t += D.pl_fx[k];
+                        ta.tk_s += D.pl_fx[k];
+                        ta.nticket = D.pl_nfx[k];
+                        ta.queue = ctr + kQueues * k + 2;
+                        HIP_TRY(launch_tb(D.wpl, ta, (ta.nticket + 3) / 4, s));
+                    }
+                    if (D.pl_sl[k] != 0xffffffffu) {
+                        ta = tb_args(ci, kTbSeal);
+                        ta.tk_t += D.pl_sl[k];
+                        ta.tk_s += D.pl_sl[k];
+                        ta.nticket = 1;
+                        ta.queue = ctr + kQueues * k + 3;
+                        HIP_TRY(launch_tb(D.wpl, ta, 1, s));
+                    }
                     const uint32_t pr = D.pl_pair[k];
                     EmitArgs e1 = ea;
                     e1.pair_xoff += pr;

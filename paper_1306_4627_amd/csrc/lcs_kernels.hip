@@ -437,14 +437,29 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// One wave per pair.  The walk of section I.D from (m, n): inside column j
-// the walk climbs to the highest row r <= i whose bit is set in
-// PM[y_j] | ~V_j; a match there is a diagonal step (emit x_r, go to
-// (r-1, j-1)), otherwise the column steps left at r.  V_j for the rows of
-// the current band (the rows one lane of the fill held) is recomputed from
-// the fill's checkpoints: NB consecutive step ranges ("tiles", 2^LOGK steps
-// each) of the band at a time, one lane per tile, each from its own
-// checkpoint and the band's stored carry-in bits.
+// The walk of section I.D: inside column j the walk climbs to the highest
+// row r <= i whose bit is set in PM[y_j] | ~V_j; a match there is a diagonal
+// step (emit x_r, go to (r-1, j-1)), otherwise the column steps left at r.
+// The walk is a function of its position alone, so two walks that reach one
+// position coincide from there on.  V_j for the rows of the current band
+// (the rows one lane of the fill held) is recomputed from the fill's
+// checkpoints: NB consecutive step ranges ("tiles", 2^LOGK steps each) of the
+// band at a time, one lane per tile, each from its own checkpoint and the
+// band's stored carry-in bits.
+//
+// A pair's rows are cut into strips of strip_bands bands, counted from row
+// 0.  Three passes, one launch each:
+//  - speculative: every strip is walked at once, the top strip from (m, n),
+//    the others from their top row and the column the straight line from
+//    (0, 0) to (m, n) crosses it at; each records the column at which it
+//    leaves every band;
+//  - fix-up: every strip below the top one is walked again from the column
+//    the speculative walk of the strip above left it at, band by band, until
+//    it leaves a band at the same column as the speculative walk of this
+//    strip (from there on the two walks coincide) -- unless it starts there;
+//  - seal: per pair, from the top, the exit of each strip is the entry of the
+//    next; a strip whose fix-up started elsewhere is walked again whole.
+// Every walk rewrites the bitmap words of the bands it crosses.
 template <int WPL, int LOGK>
 __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
     extern __shared__ uint64_t smem[];
@@ -459,204 +474,286 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
     uint64_t *tiles = pmw + sig1 * WPL;                       // [slot][o][q][V,M]
     uint16_t *ystage = (uint16_t *)(tiles + (size_t)NB * K * WPL * 2);
     uint32_t *cbstage = (uint32_t *)(ystage + (((size_t)NB * K + 3) / 4) * 4);
+    const int32_t G = (int32_t)a.strip_bands;
+    const int32_t R = G * (int32_t)BAND;                      // rows per strip
 
     for (;;) {
         uint32_t ticket = 0;
         if (lane == 0) ticket = atomicAdd(a.queue, 1u);
         ticket = __builtin_amdgcn_readfirstlane(ticket);
-        if (ticket >= a.ntb) return;
-        const uint32_t p = a.tb_pair[ticket];
-        const uint32_t item0 = a.tb_item[ticket];
-        const uint32_t lane0 = a.tb_lane0[ticket];
+        if (ticket >= a.nticket) return;
+        const uint32_t te = a.tk_t[ticket];
+        const uint32_t p = a.tb_pair[te];
+        const uint32_t item0 = a.tb_item[te];
+        const uint32_t lane0 = a.tb_lane0[te];
         const uint32_t m = a.pair_m[p];
         const uint32_t n = a.pair_n[p];
         const uint8_t *xc = a.xcodes + a.pair_xoff[p];
         uint64_t *dg = a.diag + a.pair_diag[p];
-        // the longest walks bound the kernel's duration (see k_fill)
-        if (n >= a.prio_n) __builtin_amdgcn_s_setprio(2);
-        else __builtin_amdgcn_s_setprio(0);
+        uint32_t *cross = a.cross + a.tb_band0[te];
+        uint32_t *sres = a.strip_res + 2 * (size_t)a.tb_strip0[te];
+        const int32_t S = (int32_t)((m + (uint32_t)R - 1) / (uint32_t)R);
+        int32_t s = a.mode == kTbSeal ? S - 2 : (int32_t)a.tk_s[ticket];
+        // seal: exit column of the strip above the current one
+        int32_t e = a.mode == kTbSeal ? (int32_t)cross[(S - 1) * G] : 0;
 
-        int32_t i = (int32_t)m, j = (int32_t)n;
-        int32_t band = -1, kt_hi = -1, kt_lo = 0;
-        uint32_t skew = 0, Tw = 0;
-        const uint16_t *ys = nullptr;
-        const uint64_t *ck = nullptr;
-        const uint32_t *cb = nullptr;
-        int32_t dwi = -1;          // bitmap word being filled
-        uint64_t dword = 0;
-
-        while (i > 0 && j > 0) {
-            const int32_t ell = (i - 1) / (int32_t)BAND;
-            if (ell != band) {
-                band = ell;
-                kt_hi = -1;
-                const uint32_t g = lane0 + (uint32_t)ell;
-                const uint32_t item = item0 + g / 64;
-                const uint32_t lanei = g % 64;
-                const size_t li = (size_t)item * 64 + lanei;
-                skew = a.ln_skew[li];
-                ys = a.ystream + a.ln_ys[li] - skew;
-                ck = a.ckpt + a.it_ck[item] + lanei;
-                cb = a.cbits + a.it_cb[item] + lanei;
-                Tw = a.it_T[item] / 32;
-                // match masks of this band's rows
-                for (int e = lane; e < sig1 * WPL; e += 64) pmw[e] = 0;
-                wave_lds_sync();
-                const uint32_t rb = (uint32_t)ell * BAND;
-                for (uint32_t r = lane; r < BAND; r += 64) {
-                    const uint32_t row = rb + r;
-                    if (row < m) {
-                        const uint32_t c = xc[row];
-                        atomicOr((unsigned long long *)(pmw + c * WPL + r / 64), 1ull << (r % 64));
-                    }
+        for (;;) {
+            const int32_t top = (s + 1) * R;       // first row above strip s
+            // column at which the speculative walk enters strip s
+            const uint32_t guess_raw = (uint32_t)(((uint64_t)(uint32_t)top * n) / m);
+            const int32_t guess = guess_raw < 1u ? 1 : (int32_t)guess_raw;
+            int32_t i = top, j = 0;
+            bool walk = true;
+            const bool rec = a.mode == kTbSpec;    // record band crossings
+            const bool cmp = a.mode == kTbFix;     // stop where the speculative walk is met
+            if (a.mode == kTbSpec) {
+                if (s == S - 1) {
+                    i = (int32_t)m;
+                    j = (int32_t)n;
+                } else {
+                    j = guess;
                 }
-                wave_lds_sync();
+            } else if (a.mode == kTbFix) {
+                e = (int32_t)cross[(s + 1) * G];
+                j = e;
+                walk = e != guess;
+            } else {
+                j = e;
+                walk = (int32_t)sres[2 * s] != e;
             }
-            const int32_t t = (j - 1) + (int32_t)skew;
-            const int32_t kt = t >> LOGK;
-            if (kt > kt_hi || kt < kt_lo) {
-                // recompute tiles kt-NB+1 .. kt of this band, one lane each
-                kt_hi = kt;
-                kt_lo = kt - (int32_t)NB + 1 < 0 ? 0 : kt - (int32_t)NB + 1;
-                const uint32_t sbase = (uint32_t)kt_lo << LOGK;
-                const uint32_t nsteps = (uint32_t)(kt_hi - kt_lo + 1) << LOGK;
-                for (uint32_t e = lane; e < nsteps / 2; e += 64)
-                    ((uint32_t *)ystage)[e] =
-                        (uint32_t)ys[sbase + 2 * e] | ((uint32_t)ys[sbase + 2 * e + 1] << 16);
-                for (uint32_t e = lane; e < nsteps / 32; e += 64) {
-                    const uint32_t w = (sbase >> 5) + e;
-                    cbstage[e] = w < Tw ? cb[(size_t)w * 64] : 0u;
-                }
-                wave_lds_sync();
-                const uint32_t slot = (uint32_t)lane;
-                if ((int32_t)slot <= kt_hi - kt_lo) {
-                    const int32_t ktl = kt_hi - (int32_t)slot;
-                    uint64_t V[WPL];
-#pragma unroll
-                    for (int q = 0; q < WPL; ++q) V[q] = ck[((size_t)ktl * WPL + q) * 64];
-                    const uint32_t e0 = (uint32_t)(ktl - kt_lo) << LOGK;
-                    uint64_t *tdst = tiles + (size_t)slot * K * WPL * 2;
-                    for (uint32_t o0 = 0; o0 < K; o0 += 32) {
-                        const uint32_t cw = cbstage[(e0 + o0) >> 5];
-#pragma unroll 2
-                        for (uint32_t o1 = 0; o1 < 32; o1 += 8) {
-                            // eight stream values in one 16-byte read
-                            const uint4 y8 = *(const uint4 *)(ystage + e0 + o0 + o1);
-                            const uint32_t yw[4] = {y8.x, y8.y, y8.z, y8.w};
-                            // all eight steps' match masks first: they depend on
-                            // the codes only, and reading them before any tile
-                            // write keeps each step off an LDS round trip
-                            uint64_t Mg[8][WPL];
-#pragma unroll
-                            for (int k = 0; k < 8; ++k) {
-                                const uint32_t code =
-                                    ((k & 1) ? (yw[k >> 1] >> 16) : (yw[k >> 1] & 0xffffu)) >> kShift;
-#pragma unroll
-                                for (int q = 0; q < WPL; ++q) Mg[k][q] = pmw[code * WPL + q];
+            const int32_t i_stop = s * R;
+            bool merged = false;
+            if (walk) {
+                int32_t band = -1, kt_hi = -1, kt_lo = 0;
+                uint32_t skew = 0, Tw = 0;
+                const uint16_t *ys = nullptr;
+                const uint64_t *ck = nullptr;
+                const uint32_t *cb = nullptr;
+                int32_t dwi = -1;          // bitmap word being filled
+                uint64_t dword = 0;
+                while (i > i_stop && j > 0) {
+                    const int32_t ell = (i - 1) / (int32_t)BAND;
+                    if (ell != band) {
+                        band = ell;
+                        kt_hi = -1;
+                        const uint32_t g = lane0 + (uint32_t)ell;
+                        const uint32_t item = item0 + g / 64;
+                        const uint32_t lanei = g % 64;
+                        const size_t li = (size_t)item * 64 + lanei;
+                        skew = a.ln_skew[li];
+                        ys = a.ystream + a.ln_ys[li] - skew;
+                        ck = a.ckpt + a.it_ck[item] + lanei;
+                        cb = a.cbits + a.it_cb[item] + lanei;
+                        Tw = a.it_T[item] / 32;
+                        // match masks of this band's rows
+                        for (int u = lane; u < sig1 * WPL; u += 64) pmw[u] = 0;
+                        wave_lds_sync();
+                        const uint32_t rb = (uint32_t)ell * BAND;
+                        for (uint32_t r = lane; r < BAND; r += 64) {
+                            const uint32_t row = rb + r;
+                            if (row < m) {
+                                const uint32_t c = xc[row];
+                                atomicOr((unsigned long long *)(pmw + c * WPL + r / 64), 1ull << (r % 64));
                             }
+                        }
+                        wave_lds_sync();
+                    }
+                    const int32_t t = (j - 1) + (int32_t)skew;
+                    const int32_t kt = t >> LOGK;
+                    if (kt > kt_hi || kt < kt_lo) {
+                        // recompute tiles kt-NB+1 .. kt of this band, one lane each
+                        kt_hi = kt;
+                        kt_lo = kt - (int32_t)NB + 1 < 0 ? 0 : kt - (int32_t)NB + 1;
+                        const uint32_t sbase = (uint32_t)kt_lo << LOGK;
+                        const uint32_t nsteps = (uint32_t)(kt_hi - kt_lo + 1) << LOGK;
+                        for (uint32_t u = lane; u < nsteps / 2; u += 64)
+                            ((uint32_t *)ystage)[u] =
+                                (uint32_t)ys[sbase + 2 * u] | ((uint32_t)ys[sbase + 2 * u + 1] << 16);
+                        for (uint32_t u = lane; u < nsteps / 32; u += 64) {
+                            const uint32_t w = (sbase >> 5) + u;
+                            cbstage[u] = w < Tw ? cb[(size_t)w * 64] : 0u;
+                        }
+                        wave_lds_sync();
+                        const uint32_t slot = (uint32_t)lane;
+                        if ((int32_t)slot <= kt_hi - kt_lo) {
+                            const int32_t ktl = kt_hi - (int32_t)slot;
+                            uint64_t V[WPL];
 #pragma unroll
-                            for (int k = 0; k < 8; ++k) {
-                                uint32_t carry = (cw >> (31 - (o1 + k))) & 1u;
-                                uint64_t *dst = tdst + (size_t)(o0 + o1 + k) * WPL * 2;
+                            for (int q = 0; q < WPL; ++q) V[q] = ck[((size_t)ktl * WPL + q) * 64];
+                            const uint32_t e0 = (uint32_t)(ktl - kt_lo) << LOGK;
+                            uint64_t *tdst = tiles + (size_t)slot * K * WPL * 2;
+                            for (uint32_t o0 = 0; o0 < K; o0 += 32) {
+                                const uint32_t cw = cbstage[(e0 + o0) >> 5];
+#pragma unroll 2
+                                for (uint32_t o1 = 0; o1 < 32; o1 += 8) {
+                                    // eight stream values in one 16-byte read
+                                    const uint4 y8 = *(const uint4 *)(ystage + e0 + o0 + o1);
+                                    const uint32_t yw[4] = {y8.x, y8.y, y8.z, y8.w};
+                                    // all eight steps' match masks first: they depend on
+                                    // the codes only, and reading them before any tile
+                                    // write keeps each step off an LDS round trip
+                                    uint64_t Mg[8][WPL];
 #pragma unroll
-                                for (int q = 0; q < WPL; ++q) {
-                                    const uint64_t M = Mg[k][q];
-                                    const uint64_t v = V[q];
-                                    const uint64_t U = v & M;
-                                    uint32_t c1, c2;
-                                    const uint32_t slo =
-                                        __builtin_addc((uint32_t)v, (uint32_t)U, carry, &c1);
-                                    const uint32_t shi = __builtin_addc(
-                                        (uint32_t)(v >> 32), (uint32_t)(U >> 32), c1, &c2);
-                                    carry = c2;
-                                    V[q] = ((((uint64_t)shi) << 32) | slo) | (v & ~M);
-                                    dst[q * 2] = V[q];
-                                    dst[q * 2 + 1] = M;
+                                    for (int k = 0; k < 8; ++k) {
+                                        const uint32_t code =
+                                            ((k & 1) ? (yw[k >> 1] >> 16) : (yw[k >> 1] & 0xffffu)) >> kShift;
+#pragma unroll
+                                        for (int q = 0; q < WPL; ++q) Mg[k][q] = pmw[code * WPL + q];
+                                    }
+#pragma unroll
+                                    for (int k = 0; k < 8; ++k) {
+                                        uint32_t carry = (cw >> (31 - (o1 + k))) & 1u;
+                                        uint64_t *dst = tdst + (size_t)(o0 + o1 + k) * WPL * 2;
+#pragma unroll
+                                        for (int q = 0; q < WPL; ++q) {
+                                            const uint64_t M = Mg[k][q];
+                                            const uint64_t v = V[q];
+                                            const uint64_t U = v & M;
+                                            uint32_t c1, c2;
+                                            const uint32_t slo =
+                                                __builtin_addc((uint32_t)v, (uint32_t)U, carry, &c1);
+                                            const uint32_t shi = __builtin_addc(
+                                                (uint32_t)(v >> 32), (uint32_t)(U >> 32), c1, &c2);
+                                            carry = c2;
+                                            V[q] = ((((uint64_t)shi) << 32) | slo) | (v & ~M);
+                                            dst[q * 2] = V[q];
+                                            dst[q * 2 + 1] = M;
+                                        }
+                                    }
                                 }
                             }
                         }
+                        wave_lds_sync();
                     }
-                }
-                wave_lds_sync();
-            }
-            // walk inside the resident tiles of this band.  A window of
-            // 64/WPL columns sits in lane registers, lane l holding column
-            // (tc - l/WPL), word (l % WPL); each column then costs four
-            // readlanes and scalar arithmetic on (word q, bit b) of the row.
-            const int32_t rbase = ell * (int32_t)BAND;
-            const int32_t tfloor = kt_lo << LOGK;     // first resident step
-            int32_t tc = t;
-            int32_t q = (i - 1 - rbase) >> 6;
-            int32_t b = (i - 1 - rbase) & 63;
-            const int32_t wq0 = rbase >> 6;           // bitmap word of the band's word 0
-            bool leave = false;
-            while (!leave) {
-                const int32_t tl = tc - (int32_t)(lane / WPL);
-                uint64_t VL = 0, ML = 0;
-                if (tl >= tfloor) {
-                    const uint32_t sl = (uint32_t)(kt_hi - (tl >> LOGK));
-                    const uint64_t *e =
-                        tiles + (((size_t)sl << LOGK) + ((uint32_t)tl & (K - 1))) * WPL * 2 +
-                        (lane % WPL) * 2;
-                    VL = e[0];
-                    ML = e[1];
-                }
-                if (wq0 + q != dwi) {
-                    if (dwi >= 0 && dword && lane == 0) dg[dwi] = dword;
-                    dwi = wq0 + q;
-                    dword = 0;
-                }
-                const int32_t avail = tc - tfloor + 1;    // columns resident from tc down
-                int32_t kmax = avail < (int32_t)(64 / WPL) ? avail : (int32_t)(64 / WPL);
-                kmax = kmax < j ? kmax : j;
-                int32_t k = 0;
-                for (; k < kmax; ++k) {
-                    int32_t idx = k * WPL + q;
-                    uint64_t Vw = readlane64(VL, idx), Mw = readlane64(ML, idx);
-                    uint64_t cand = (Mw | ~Vw) & (~0ull >> (63 - b));
-                    if (__builtin_expect(cand == 0, 0)) {
-                        // up through the rest of word q: continue in the words below
-                        while (cand == 0 && q > 0) {
-                            if (dword && lane == 0) dg[dwi] = dword;
-                            --q;
-                            --idx;
-                            --dwi;
+                    // walk inside the resident tiles of this band.  A window holds
+                    // word q of 64 consecutive columns in lane registers, lane l
+                    // holding column tc - l.  A diagonal step at row b of column k
+                    // happens exactly when the match bit M_k[b] is set (a set match
+                    // bit is the highest candidate at or below b), so a run of
+                    // diagonal steps is found at once: lane l tests bit b - (l - k)
+                    // of its match word and the run is the count of consecutive set
+                    // ballot bits from lane k.  Other steps take the top candidate
+                    // bit of PM[y_j] | ~V_j at or below b.  Every bitmap word the
+                    // walk passes through is written whole.
+                    const int32_t rbase = ell * (int32_t)BAND;
+                    const int32_t tfloor = kt_lo << LOGK;     // first resident step
+                    int32_t tc = t;
+                    int32_t q = (i - 1 - rbase) >> 6;
+                    int32_t b = (i - 1 - rbase) & 63;
+                    const int32_t wq0 = rbase >> 6;           // bitmap word of the band's word 0
+                    bool leave = false;
+                    while (!leave) {
+                        const int32_t tl = tc - lane;
+                        uint64_t VL = 0, ML = 0;
+                        if (tl >= tfloor) {
+                            const uint32_t sl = (uint32_t)(kt_hi - (tl >> LOGK));
+                            const uint64_t *tp =
+                                tiles + (((size_t)sl << LOGK) + ((uint32_t)tl & (K - 1))) * WPL * 2 + q * 2;
+                            VL = tp[0];
+                            ML = tp[1];
+                        }
+                        if (wq0 + q != dwi) {
+                            if (dwi >= 0 && lane == 0) dg[dwi] = dword;
+                            dwi = wq0 + q;
                             dword = 0;
-                            b = 63;
-                            Vw = readlane64(VL, idx);
-                            Mw = readlane64(ML, idx);
-                            cand = Mw | ~Vw;
                         }
-                        if (cand == 0) {  // left the band upward in this column
-                            b = -1;
-                            leave = true;
-                            break;
-                        }
-                    }
-                    const int32_t r = 63 - (int32_t)__builtin_clzll(cand);
-                    const uint32_t d = (uint32_t)(Mw >> r) & 1u;
-                    dword |= (uint64_t)d << r;
-                    b = r - (int32_t)d;
-                    if (__builtin_expect(b < 0, 0)) {
-                        if (q == 0) {     // diagonal step out of the band
+                        const int32_t avail = tc - tfloor + 1;    // columns resident from tc down
+                        int32_t kmax = avail < 64 ? avail : 64;
+                        kmax = kmax < j ? kmax : j;
+                        int32_t k = 0;
+                        while (k < kmax) {
+                            // diagonal run from (b, k)
+                            const int32_t sh = b + k - lane;
+                            const bool bit = lane >= k && lane < kmax && sh >= 0 && ((ML >> (sh & 63)) & 1ull);
+                            const uint64_t dm = __builtin_amdgcn_ballot_w64(bit) >> k;
+                            const uint64_t nz = ~dm;
+                            const int32_t run = nz ? (int32_t)__builtin_ctzll(nz) : 64;
+                            if (run > 0) {
+                                const uint64_t ones = run >= 64 ? ~0ull : ((1ull << run) - 1);
+                                dword |= ones << (b - run + 1);
+                                b -= run;
+                                k += run;
+                                if (b < 0) {
+                                    if (q == 0) { leave = true; break; }   // out of the band, downward
+                                    if (lane == 0) dg[dwi] = dword;
+                                    --q;
+                                    --dwi;
+                                    dword = 0;
+                                    b = 63;
+                                    break;
+                                }
+                                continue;
+                            }
+                            // one general step at column k
+                            const uint64_t Vw = readlane64(VL, k), Mw = readlane64(ML, k);
+                            const uint64_t cand = (Mw | ~Vw) & (~0ull >> (63 - b));
+                            if (cand == 0) {
+                                // up through the rest of word q in this column
+                                if (q == 0) { b = -1; leave = true; break; }
+                                if (lane == 0) dg[dwi] = dword;
+                                --q;
+                                --dwi;
+                                dword = 0;
+                                b = 63;
+                                break;
+                            }
+                            const int32_t r = 63 - (int32_t)__builtin_clzll(cand);
+                            const uint32_t d = (uint32_t)(Mw >> r) & 1u;
+                            dword |= (uint64_t)d << r;
+                            b = r - (int32_t)d;
                             ++k;
-                            leave = true;
+                            if (b < 0) {
+                                if (q == 0) { leave = true; break; }
+                                if (lane == 0) dg[dwi] = dword;
+                                --q;
+                                --dwi;
+                                dword = 0;
+                                b = 63;
+                                break;
+                            }
+                        }
+                        j -= k;
+                        tc -= k;
+                        if (j == 0 || tc < tfloor) leave = true;
+                    }
+                    i = rbase + q * 64 + b + 1;
+                    if (i == rbase) {
+                        // left band ell through its bottom row
+                        if (lane == 0) dg[dwi] = dword;
+                        dwi = -1;
+                        dword = 0;
+                        if (rec && lane == 0) cross[ell] = (uint32_t)j;
+                        if (cmp && (int32_t)cross[ell] == j) {
+                            merged = true;
                             break;
                         }
-                        if (dword && lane == 0) dg[dwi] = dword;
-                        --q;
-                        --dwi;
-                        dword = 0;
-                        b = 63;
                     }
                 }
-                j -= k;
-                tc -= k;
-                if (j == 0 || tc < tfloor) leave = true;
+                if (!merged) {
+                    if (dwi >= 0 && lane == 0) dg[dwi] = dword;
+                    if (j == 0 && i > i_stop) {
+                        // the walk ended inside the strip: rows i_stop+1..i
+                        // take no diagonal step
+                        if (rec)
+                            for (int32_t g = i_stop / (int32_t)BAND + lane; g <= (i - 1) / (int32_t)BAND;
+                                 g += 64)
+                                cross[g] = 0;
+                        if (!rec)
+                            for (int32_t w = i_stop / 64 + lane; w < i / 64; w += 64) dg[w] = 0;
+                    }
+                }
             }
-            i = rbase + q * 64 + b + 1;
+            if (a.mode == kTbFix) {
+                if (lane == 0) {
+                    sres[2 * s] = (uint32_t)e;
+                    sres[2 * s + 1] = (!walk || merged) ? cross[s * G] : (uint32_t)j;
+                }
+            } else if (a.mode == kTbSeal) {
+                e = walk ? j : (int32_t)sres[2 * s + 1];
+            }
+            if (a.mode != kTbSeal || s == 0) break;
+            --s;
         }
-        if (dwi >= 0 && dword && lane == 0) dg[dwi] = dword;
     }
 }
 

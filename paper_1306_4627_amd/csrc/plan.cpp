@@ -206,6 +206,30 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
             tp.push_back(C.tb_pair[o]); ti.push_back(C.tb_item[o]); tl.push_back(C.tb_lane0[o]);
         }
         C.tb_pair.swap(tp); C.tb_item.swap(ti); C.tb_lane0.swap(tl);
+        if (cfg.traceback) {
+            const uint64_t band = (uint64_t)kLanes * wpl;
+            const uint64_t rows = std::max<uint64_t>((uint64_t)std::max(cfg.strip_rows, 1), band);
+            C.strip_bands = (uint32_t)ceil_div(rows, band);
+            for (size_t t = 0; t < C.tb_pair.size(); ++t) {
+                const uint64_t nb = ceil_div(pairs[C.tb_pair[t]].m, band);
+                const uint64_t S = ceil_div(nb, (uint64_t)C.strip_bands);
+                if (C.n_bands + nb > 0xffffffffull || C.n_strips + S > 0xffffffffull)
+                    return "too many traceback bands";
+                C.tb_band0.push_back((uint32_t)C.n_bands);
+                C.tb_strip0.push_back((uint32_t)C.n_strips);
+                C.n_bands += nb;
+                C.n_strips += S;
+                for (uint64_t s = S; s-- > 0;) {
+                    C.sp_t.push_back((uint32_t)t);
+                    C.sp_s.push_back((uint32_t)s);
+                    if (s + 1 < S) {
+                        C.fx_t.push_back((uint32_t)t);
+                        C.fx_s.push_back((uint32_t)s);
+                    }
+                }
+                if (S >= 2) C.sl_t.push_back((uint32_t)t);
+            }
+        }
         out.items += nit;
         out.lanes += nit * kLanes;
         out.lane_steps += C.lane_steps;
@@ -359,6 +383,50 @@ std::string check_plan(const std::vector<PairShape> &pairs, const Plan &p) {
                     ok = true;
             if (!ok) return "idle lane without a sentinel region";
         }
+    }
+    // traceback strips: every strip of every traceback pair has exactly one
+    // speculative ticket, every strip below the top one one fix-up ticket,
+    // and the band and strip tables tile their arrays in entry order
+    for (const ClassPlan &C : p.classes) {
+        if (!p.cfg.traceback) break;
+        const size_t nt = C.tb_pair.size();
+        if (C.tb_band0.size() != nt || C.tb_strip0.size() != nt) return "strip table size";
+        const uint64_t band = (uint64_t)kLanes * C.wpl;
+        uint64_t b0 = 0, s0 = 0, nseal = 0;
+        for (size_t t = 0; t < nt; ++t) {
+            const uint64_t nb = (pairs[C.tb_pair[t]].m + band - 1) / band;
+            const uint64_t S = (nb + C.strip_bands - 1) / C.strip_bands;
+            if (C.tb_band0[t] != b0 || C.tb_strip0[t] != s0) return "strip tables not contiguous";
+            b0 += nb;
+            s0 += S;
+            nseal += S >= 2;
+        }
+        if (b0 != C.n_bands || s0 != C.n_strips) return "strip totals";
+        std::vector<std::vector<uint8_t>> seen_sp(nt), seen_fx(nt);
+        for (size_t t = 0; t < nt; ++t) {
+            const uint64_t nb = (pairs[C.tb_pair[t]].m + band - 1) / band;
+            const uint64_t S = (nb + C.strip_bands - 1) / C.strip_bands;
+            seen_sp[t].assign(S, 0);
+            seen_fx[t].assign(S, 0);
+        }
+        if (C.sp_t.size() != C.sp_s.size() || C.fx_t.size() != C.fx_s.size()) return "ticket arrays";
+        for (size_t k = 0; k < C.sp_t.size(); ++k) {
+            if (C.sp_t[k] >= nt || C.sp_s[k] >= seen_sp[C.sp_t[k]].size()) return "speculative ticket range";
+            if (seen_sp[C.sp_t[k]][C.sp_s[k]]++) return "strip walked twice";
+        }
+        for (size_t k = 0; k < C.fx_t.size(); ++k) {
+            if (C.fx_t[k] >= nt || C.fx_s[k] + 1 >= seen_fx[C.fx_t[k]].size()) return "fix-up ticket range";
+            if (seen_fx[C.fx_t[k]][C.fx_s[k]]++) return "strip fixed twice";
+        }
+        for (size_t t = 0; t < nt; ++t) {
+            for (size_t s = 0; s < seen_sp[t].size(); ++s) {
+                if (!seen_sp[t][s]) return "strip without a speculative walk";
+                if (s + 1 < seen_sp[t].size() && !seen_fx[t][s]) return "strip without a fix-up";
+            }
+        }
+        if (C.sl_t.size() != nseal) return "seal tickets";
+        for (size_t k = 0; k < C.sl_t.size(); ++k)
+            if (C.sl_t[k] >= nt || seen_sp[C.sl_t[k]].size() < 2) return "seal ticket";
     }
     // regions do not overlap
     std::vector<std::pair<uint64_t, uint64_t>> iv;

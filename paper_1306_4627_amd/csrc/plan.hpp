@@ -43,6 +43,7 @@ struct PlanConfig {
     int ckpt = 128;         // steps between stored V checkpoints (multiple of kChunk)
     int sigma = 4;          // alphabet size; code sigma is the zero-mask sentinel
     bool plain = false;     // one pair per item, no packing
+    int strip_rows = 2048;  // rows per traceback strip (rounded up to whole bands)
 };
 
 // One class = one fill launch with a fixed words-per-lane.
@@ -65,6 +66,19 @@ struct ClassPlan {
     std::vector<uint32_t> tb_pair;
     std::vector<uint32_t> tb_item;    // item holding the segment's first lane
     std::vector<uint32_t> tb_lane0;   // lane of that item
+    // Traceback strips.  A band is the rows one lane holds (64*wpl rows); a
+    // strip is strip_bands consecutive bands of one pair, counted from row
+    // 0, so a pair has S = ceil(bands / strip_bands) strips and strip S-1
+    // (the top one) may be short.  Per traceback entry: its first band
+    // crossing and first strip result.  Tickets: the speculative pass has
+    // one per strip, the fix-up pass one per strip below the top one, the
+    // seal pass one per pair with at least two strips.
+    uint32_t strip_bands = 1;
+    std::vector<uint32_t> tb_band0, tb_strip0;
+    std::vector<uint32_t> sp_t, sp_s;   // speculative tickets: entry, strip
+    std::vector<uint32_t> fx_t, fx_s;   // fix-up tickets: entry, strip
+    std::vector<uint32_t> sl_t;         // seal tickets: entry
+    uint64_t n_bands = 0, n_strips = 0;
     uint64_t ck_words = 0, cb_words = 0, xf_words = 0;
     uint64_t lane_steps = 0;
 };

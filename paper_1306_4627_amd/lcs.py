@@ -54,7 +54,8 @@ class lcs_pair(ctypes.Structure):
 
 class lcs_tuning(ctypes.Structure):
     _fields_ = [("words_per_lane", ctypes.c_int32), ("ckpt_interval", ctypes.c_int32),
-                ("persistent_waves", ctypes.c_int32), ("plain", ctypes.c_int32)]
+                ("persistent_waves", ctypes.c_int32), ("plain", ctypes.c_int32),
+                ("strip_rows", ctypes.c_int32), ("tb_tiles", ctypes.c_int32)]
 
 
 class lcs_batch_stats(ctypes.Structure):
@@ -72,6 +73,14 @@ def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_1306_4627_amd/build.py "
                           "(no CPU fallback exists)")
+    # One HIP runtime per process.  PyTorch ships its own libamdhip64 and
+    # links it under another name than this library's; loaded first, it
+    # satisfies this library's dependency too, so device memory and streams
+    # are shared and the device is never opened by two runtimes.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     u8p, u64p, vp = P(ctypes.c_uint8), P(ctypes.c_uint64), ctypes.c_void_p
@@ -181,8 +190,10 @@ def _alpha(a) -> Alphabet:
     return Alphabet(bytes(a))
 
 
-def _tuning(words_per_lane=0, ckpt_interval=0, persistent_waves=0, plain=False):
-    return lcs_tuning(int(words_per_lane), int(ckpt_interval), int(persistent_waves), int(bool(plain)))
+def _tuning(words_per_lane=0, ckpt_interval=0, persistent_waves=0, plain=False, strip_rows=0,
+            tb_tiles=0):
+    return lcs_tuning(int(words_per_lane), int(ckpt_interval), int(persistent_waves), int(bool(plain)),
+                      int(strip_rows), int(tb_tiles))
 
 
 class _Pairs:
@@ -287,7 +298,8 @@ class Batch:
 
     def __init__(self, ctx: Context, pairs, alphabet="dna", traceback: bool = False,
                  graph: bool = False, words_per_lane: int = 0, ckpt_interval: int = 0,
-                 persistent_waves: int = 0, plain: bool = False):
+                 persistent_waves: int = 0, plain: bool = False, strip_rows: int = 0,
+                 tb_tiles: int = 0):
         self.ctx = ctx
         self._pairs = _Pairs(pairs)
         self.count = self._pairs.count
@@ -295,7 +307,7 @@ class Batch:
         self.traceback = traceback
         self.cap = sum(min(len(_as_u8(x)), len(_as_u8(y))) for x, y in pairs)
         flags = (LCS_WANT_TRACEBACK if traceback else 0) | (LCS_USE_GRAPH if graph else 0)
-        t = _tuning(words_per_lane, ckpt_interval, persistent_waves, plain)
+        t = _tuning(words_per_lane, ckpt_interval, persistent_waves, plain, strip_rows, tb_tiles)
         h = ctypes.c_void_p()
         _check(_lib.lcs_batch_create(ctx.h, self._pairs.ptr(), self.count,
                                      ctypes.byref(self._alpha.c), flags, ctypes.byref(t),

@@ -105,6 +105,64 @@ def test_traceback_checkpoint_intervals(ctx, lcs, ckpt):
         assert b.tracebacks() == _oracle_tracebacks(pairs)
 
 
+def _strip_cases(g):
+    pairs = []
+    for _ in range(24):          # related: the straight-line entry guess is close
+        m = int(g.integers(1, 6000))
+        x = _rand(g, m, inputs.DNA)
+        y, _ = inputs.mutate(g, x, float(g.uniform(0.02, 0.4)), inputs.DNA)
+        pairs.append((x, y))
+    for _ in range(8):           # unrelated, lopsided: guesses far from the path
+        m, n = int(g.integers(1, 4000)), int(g.integers(1, 4000))
+        pairs.append((_rand(g, m, inputs.DNA), _rand(g, n, inputs.DNA)))
+    A = lambda k: np.full(k, ord("A"), np.uint8)
+    C = lambda k: np.full(k, ord("C"), np.uint8)
+    pairs += [
+        (A(3000), A(500)),                                    # walk ends high up
+        (A(500), A(3000)),
+        (A(2000), C(1500)),                                   # no match at all
+        (A(3000), np.concatenate([C(1000), A(40), C(1000)])),  # short diagonal, long climbs
+        (np.frombuffer(b"ACGT" * 700, np.uint8), np.frombuffer(b"CGTA" * 650, np.uint8)),
+        (_rand(g, 2500, inputs.DNA), _rand(g, 3, inputs.DNA)),
+    ]
+    return pairs
+
+
+@pytest.mark.parametrize("strip_rows,wpl", [(64, 1), (128, 2), (192, 1), (512, 2), (1024, 4)])
+def test_traceback_strips(ctx, lcs, strip_rows, wpl):
+    # the walk of each pair is cut into strips walked from estimated entry
+    # columns and then reconciled; the result must not depend on the cut
+    g = inputs.rng(6450 + strip_rows + wpl)
+    pairs = _strip_cases(g)
+    _say(f"strips rows={strip_rows} wpl={wpl} pairs={len(pairs)}")
+    with lcs.Batch(ctx, pairs, "dna", traceback=True, words_per_lane=wpl,
+                   strip_rows=strip_rows) as b:
+        b.run()
+        L = b.lengths()
+        S = b.tracebacks()
+    assert np.array_equal(L, _oracle_lengths(pairs))
+    want = _oracle_tracebacks(pairs)
+    for k, (a, w) in enumerate(zip(S, want)):
+        assert a == w, f"pair {k}: m={len(pairs[k][0])} n={len(pairs[k][1])}"
+
+
+@pytest.mark.parametrize("tiles", [1, 3, 8])
+def test_traceback_strips_plain_and_tiles(ctx, lcs, tiles):
+    g = inputs.rng(6470 + tiles)
+    pairs = _strip_cases(g)[::3]
+    want = _oracle_tracebacks(pairs)
+    _say(f"strips plain tiles={tiles} pairs={len(pairs)}")
+    with lcs.Batch(ctx, pairs, "dna", traceback=True, plain=True, strip_rows=256,
+                   tb_tiles=tiles) as b:
+        b.run()
+        assert b.tracebacks() == want
+    with lcs.Batch(ctx, pairs, "dna", traceback=True, graph=True, strip_rows=128,
+                   tb_tiles=tiles) as b:
+        for rep in range(2):
+            b.run()
+            assert b.tracebacks() == want, rep
+
+
 @pytest.mark.parametrize("wpl", [1, 2, 4])
 def test_chained_items_long_rows(ctx, lcs, wpl):
     # rows beyond one wave (64 lanes * wpl words * 64 bits) chain several
