@@ -95,8 +95,12 @@ typedef struct lcs_batch lcs_batch;
  *                    split into strips walked in parallel from estimated
  *                    entry columns and then reconciled; the result does not
  *                    depend on this value;
- *  tb_tiles        : checkpoint intervals of one band the traceback
- *                    recomputes at once (1..8, default 2). */
+ *  tb_tiles        : checkpoint intervals per band the traceback
+ *                    recomputes at once (1..8, default 2, or 1 for wide
+ *                    bands);
+ *  tb_bands        : bands the traceback recomputes at once (1..16,
+ *                    tb_tiles * tb_bands <= 64; default: as many, up to 4,
+ *                    as fit about 10 KiB of LDS per wave). */
 typedef struct {
     int32_t words_per_lane;
     int32_t ckpt_interval;
@@ -104,6 +108,7 @@ typedef struct {
     int32_t plain;
     int32_t strip_rows;
     int32_t tb_tiles;
+    int32_t tb_bands;
 } lcs_tuning;
 
 /* What a batch was planned into (filled by lcs_batch_info). */

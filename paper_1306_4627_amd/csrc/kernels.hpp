@@ -93,7 +93,8 @@ struct TbArgs {
     int32_t mode;               // kTbSpec, kTbFix or kTbSeal
     int32_t sigma;
     int32_t ckpt_every;
-    int32_t nb;                 // tiles recomputed together (one per lane)
+    int32_t nb;                 // tiles per band recomputed together (one per lane)
+    int32_t nbands;             // bands per recompute round
 };
 
 // Traceback passes over strips (runs of bands of one pair): speculative
@@ -121,7 +122,7 @@ constexpr int kFillBlock = 256;   // four independent waves per work-group
 constexpr int kTbBlock = 256;
 
 size_t fill_lds_bytes(int wpl, int sigma);
-size_t tb_lds_bytes(int wpl, int sigma, int ckpt_every, int nb);
+size_t tb_lds_bytes(int wpl, int sigma, int ckpt_every, int nb, int bands);
 
 const void *fill_symbol(int wpl, bool tb);
 const void *tb_symbol(int wpl, int ckpt_every);

@@ -53,7 +53,8 @@ struct ClassDev {
     uint32_t *plain_ctr = nullptr;     // plain mode: kQueues queue counters per pair
     uint32_t *q_fill = nullptr, *q_spec = nullptr, *q_fix = nullptr, *q_seal = nullptr;
     uint32_t fill_grid = 1, sp_grid = 1, fx_grid = 1, sl_grid = 1;
-    int nb = 1;                        // traceback tiles recomputed together
+    int nb = 1;                        // traceback tiles per band recomputed together
+    int nbands = 1;                    // traceback bands recomputed together
     uint32_t prio_T = 0xffffffffu;     // fill items this long run at raised priority
     // plain mode: one launch per pair and pass
     std::vector<uint32_t> pl_pair;     // pair of each launch
@@ -189,7 +190,9 @@ static lcs_status check_tuning(const lcs_tuning *t) {
         t->ckpt_interval != 256)
         return LCS_ERR_ARG;
     if (t->persistent_waves < 0 || t->plain < 0 || t->plain > 1) return LCS_ERR_ARG;
-    if (t->strip_rows < 0 || t->tb_tiles < 0 || t->tb_tiles > 8) return LCS_ERR_ARG;
+    if (t->strip_rows < 0 || t->tb_tiles < 0 || t->tb_tiles > 8 || t->tb_bands < 0 ||
+        t->tb_bands > 16 || t->tb_tiles * t->tb_bands > 64)
+        return LCS_ERR_ARG;
     return LCS_OK;
 }
 
@@ -597,10 +600,21 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
             for (uint32_t T : C.it_T) mt = std::max(mt, T);
             D.prio_T = std::max<uint32_t>(mt / 2, 1);
         }
-        D.nb = (tuning && tuning->tb_tiles) ? tuning->tb_tiles : 2;
+        // traceback recompute rounds: by default two tiles per band and as
+        // many bands (up to four) as fit about 10 KiB of LDS per wave (more
+        // LDS per wave costs more in resident waves than it saves in rounds)
+        {
+            const size_t slot = tb_lds_bytes(C.wpl, sigma, cfg.ckpt, 1, 1) / (kTbBlock / 64);
+            D.nb = (tuning && tuning->tb_tiles) ? tuning->tb_tiles : (slot > 6 * 1024 ? 1 : 2);
+            const int fit = (int)((10 * 1024) / (slot * D.nb));
+            D.nbands = (tuning && tuning->tb_bands) ? tuning->tb_bands : std::max(1, std::min(4, fit));
+            if (D.nb * D.nbands > 64 ||
+                tb_lds_bytes(C.wpl, sigma, cfg.ckpt, D.nb, D.nbands) > 160 * 1024)
+                return fail(LCS_ERR_ARG);
+        }
         {
             const void *sym = tb_symbol(C.wpl, cfg.ckpt);
-            const size_t lds = tb_lds_bytes(C.wpl, sigma, cfg.ckpt, D.nb);
+            const size_t lds = tb_lds_bytes(C.wpl, sigma, cfg.ckpt, D.nb, D.nbands);
             D.sp_grid = resident_grid(ctx, sym, lds, (D.nsp + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
             D.fx_grid = resident_grid(ctx, sym, lds, (D.nfx + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
             D.sl_grid = resident_grid(ctx, sym, lds, (D.nsl + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
@@ -734,6 +748,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         ta.sigma = b->sigma;
         ta.ckpt_every = b->ckpt;
         ta.nb = D.nb;
+        ta.nbands = D.nbands;
         ta.mode = mode;
         if (mode == kTbSpec) {
             ta.tk_t = D.sp_t;

@@ -413,16 +413,24 @@ hipError_t launch_fill(int wpl, bool tb, const FillArgs &a, uint32_t grid, hipSt
 // traceback
 // --------------------------------------------------------------------------
 
-// Per-wave LDS of the walk, in 64-bit words: the band's match masks, NB
-// recomputed tiles of (V, M) words, the tiles' stream values and carry-in
-// words.
-__host__ __device__ static inline size_t tb_wave_words(int wpl, int sigma, int K, int nb) {
-    return (size_t)(sigma + 1) * wpl + (size_t)nb * K * wpl * 2 + ((size_t)nb * K + 3) / 4 +
-           ((size_t)nb * K / 32 + 1 + 1) / 2;
+// Per-wave LDS of the walk, in 64-bit words.  A recompute round covers up
+// to `bands` consecutive bands with `nb` tiles each (a slot per tile): the
+// bands' match masks, the V words of every slot (each slot padded by two
+// words so that the slots start in different LDS banks), the slots' stream
+// values and carry-in words, and per band the first and last resident tile.
+__host__ __device__ static inline size_t tb_slot_words(int wpl, int K) { return (size_t)K * wpl + 2; }
+
+// Every region starts on a 16-byte boundary (an even word count before it).
+__host__ __device__ static inline size_t tb_even(size_t w) { return (w + 1) & ~(size_t)1; }
+
+__host__ __device__ static inline size_t tb_wave_words(int wpl, int sigma, int K, int nb, int bands) {
+    const size_t slots = (size_t)nb * bands;
+    return tb_even((size_t)bands * (sigma + 1) * wpl) + slots * tb_slot_words(wpl, K) +
+           tb_even(slots * K / 4) + tb_even(slots * K / 64) + tb_even((size_t)bands);
 }
 
-size_t tb_lds_bytes(int wpl, int sigma, int K, int nb) {
-    return (size_t)(kTbBlock / 64) * tb_wave_words(wpl, sigma, K, nb) * sizeof(uint64_t);
+size_t tb_lds_bytes(int wpl, int sigma, int K, int nb, int bands) {
+    return (size_t)(kTbBlock / 64) * tb_wave_words(wpl, sigma, K, nb, bands) * sizeof(uint64_t);
 }
 
 // Lane `idx` (wave-uniform) of a 64-bit per-lane value, as a scalar.
@@ -437,22 +445,72 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// V of one band over the 2^LOGK steps of one tile, from the checkpoint V0
+// before its first step: the fill's column recurrence with the stored
+// carry-in bits (most significant bit first, one 32-bit word per 32 steps),
+// V after every step stored to dst.  The carry-in bit of a step becomes the
+// carry lane mask by adding the carry word to itself (its top bit is the
+// carry out); two wait states follow that VALU write before the first add
+// reads the mask.
+template <int WPL, int LOGK>
+__device__ __forceinline__ void recompute_tile(uint64_t *dst, const uint64_t *pmd, const uint16_t *yst,
+                                               const uint32_t *cbs, const uint64_t (&V0)[WPL]) {
+    constexpr uint32_t K = 1u << LOGK;
+    constexpr uint32_t kShift = 9 + (WPL == 1 ? 0 : WPL == 2 ? 1 : WPL == 4 ? 2 : 3);
+    uint32_t vlo[WPL], vhi[WPL];
+#pragma unroll
+    for (int q = 0; q < WPL; ++q) {
+        vlo[q] = (uint32_t)V0[q];
+        vhi[q] = (uint32_t)(V0[q] >> 32);
+    }
+    for (uint32_t o0 = 0; o0 < K; o0 += 32) {
+        uint32_t cw = cbs[o0 >> 5];
+#pragma unroll
+        for (uint32_t o1 = 0; o1 < 32; o1 += 8) {
+            // eight stream values in one 16-byte read, then all eight steps'
+            // match masks before any store of this group
+            const uint4 y8 = *(const uint4 *)(yst + o0 + o1);
+            const uint32_t yw[4] = {y8.x, y8.y, y8.z, y8.w};
+            uint64_t Mg[8][WPL];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t code = ((k & 1) ? (yw[k >> 1] >> 16) : (yw[k >> 1] & 0xffffu)) >> kShift;
+#pragma unroll
+                for (int q = 0; q < WPL; ++q) Mg[k][q] = pmd[code * WPL + q];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                uint64_t carry;
+                asm("v_add_co_u32 %[cw], %[c], %[cw], %[cw]\n\t"
+                    "s_nop 1"
+                    : [cw] "+v"(cw), [c] "=s"(carry));
+                column_step<WPL>(vlo, vhi, Mg[k], carry);
+                uint64_t *d = dst + (size_t)(o0 + o1 + k) * WPL;
+#pragma unroll
+                for (int q = 0; q < WPL; ++q) d[q] = ((uint64_t)vhi[q] << 32) | vlo[q];
+            }
+        }
+    }
+}
+
 // The walk of section I.D: inside column j the walk climbs to the highest
 // row r <= i whose bit is set in PM[y_j] | ~V_j; a match there is a diagonal
 // step (emit x_r, go to (r-1, j-1)), otherwise the column steps left at r.
 // The walk is a function of its position alone, so two walks that reach one
-// position coincide from there on.  V_j for the rows of the current band
-// (the rows one lane of the fill held) is recomputed from the fill's
-// checkpoints: NB consecutive step ranges ("tiles", 2^LOGK steps each) of the
-// band at a time, one lane per tile, each from its own checkpoint and the
-// band's stored carry-in bits.
+// position coincide from there on.  V_j for the rows of a band (the rows one
+// lane of the fill held) is recomputed from the fill's checkpoints in tiles
+// of 2^LOGK steps, one lane per tile, each from its own checkpoint and the
+// band's stored carry-in bits.  A round recomputes nb tiles for each of up
+// to nbands bands below the walk's position: the tiles ending at the walk's
+// column for the band it is in, and for the next bands the tiles around the
+// column the straight line from (0, 0) to (m, n) predicts for them.  A band
+// whose tiles miss the walk starts a new round.
 //
 // A pair's rows are cut into strips of strip_bands bands, counted from row
 // 0.  Three passes, one launch each:
 //  - speculative: every strip is walked at once, the top strip from (m, n),
-//    the others from their top row and the column the straight line from
-//    (0, 0) to (m, n) crosses it at; each records the column at which it
-//    leaves every band;
+//    the others from their top row and the column the straight line crosses
+//    it at; each records the column at which it leaves every band;
 //  - fix-up: every strip below the top one is walked again from the column
 //    the speculative walk of the strip above left it at, band by band, until
 //    it leaves a band at the same column as the speculative walk of this
@@ -468,14 +526,19 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
     constexpr uint32_t kShift = 9 + (WPL == 1 ? 0 : WPL == 2 ? 1 : WPL == 4 ? 2 : 3);
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int sig1 = a.sigma + 1;
-    const uint32_t NB = (uint32_t)a.nb;
-    uint64_t *pmw = smem + (size_t)wv * tb_wave_words(WPL, a.sigma, (int)K, (int)NB);
-    uint64_t *tiles = pmw + sig1 * WPL;                       // [slot][o][q][V,M]
-    uint16_t *ystage = (uint16_t *)(tiles + (size_t)NB * K * WPL * 2);
-    uint32_t *cbstage = (uint32_t *)(ystage + (((size_t)NB * K + 3) / 4) * 4);
+    const int32_t sig1 = a.sigma + 1;
+    const int32_t NB = a.nb;
+    const int32_t NBD = a.nbands;
+    const uint32_t SW = (uint32_t)tb_slot_words(WPL, (int)K);
+    uint64_t *pm = smem + (size_t)wv * tb_wave_words(WPL, a.sigma, (int)K, NB, NBD);  // [band][sig1][WPL]
+    const size_t NS = (size_t)NB * NBD;                                               // slots
+    uint64_t *tiles = pm + tb_even((size_t)NBD * sig1 * WPL);                          // [slot][K][WPL] + pad
+    uint16_t *ystage = (uint16_t *)(tiles + NS * SW);                                  // [slot][K]
+    uint32_t *cbstage = (uint32_t *)((uint64_t *)ystage + tb_even(NS * K / 4));        // [slot][K/32]
+    int2 *bmeta = (int2 *)((uint64_t *)cbstage + tb_even(NS * K / 64));              // [band] {lo, hi}
     const int32_t G = (int32_t)a.strip_bands;
     const int32_t R = G * (int32_t)BAND;                      // rows per strip
+    const int32_t margin = NB * (int32_t)K / 4;
 
     for (;;) {
         uint32_t ticket = 0;
@@ -524,119 +587,216 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
             const int32_t i_stop = s * R;
             bool merged = false;
             if (walk) {
-                int32_t band = -1, kt_hi = -1, kt_lo = 0;
-                uint32_t skew = 0, Tw = 0;
-                const uint16_t *ys = nullptr;
-                const uint64_t *ck = nullptr;
-                const uint32_t *cb = nullptr;
+                int32_t band = -1, rtop = -1, nbr = 0, dsl = 0, klo = 0, khi = -1;
+                uint32_t skew = 0;
                 int32_t dwi = -1;          // bitmap word being filled
                 uint64_t dword = 0;
+                // per-band data of up to 64 bands md_lo.. (lane g: band
+                // md_lo + g): skew, stream offset of step 0, checkpoint and
+                // carry-bit offsets, carry words stored
+                const int32_t band_lo = i_stop / (int32_t)BAND;
+                int32_t md_lo = 0x7fffffff;
+                uint32_t v_skew = 0, v_tw = 0;
+                uint64_t v_yso = 0, v_cko = 0, v_cbo = 0;
                 while (i > i_stop && j > 0) {
                     const int32_t ell = (i - 1) / (int32_t)BAND;
                     if (ell != band) {
                         band = ell;
-                        kt_hi = -1;
-                        const uint32_t g = lane0 + (uint32_t)ell;
-                        const uint32_t item = item0 + g / 64;
-                        const uint32_t lanei = g % 64;
-                        const size_t li = (size_t)item * 64 + lanei;
-                        skew = a.ln_skew[li];
-                        ys = a.ystream + a.ln_ys[li] - skew;
-                        ck = a.ckpt + a.it_ck[item] + lanei;
-                        cb = a.cbits + a.it_cb[item] + lanei;
-                        Tw = a.it_T[item] / 32;
-                        // match masks of this band's rows
-                        for (int u = lane; u < sig1 * WPL; u += 64) pmw[u] = 0;
-                        wave_lds_sync();
-                        const uint32_t rb = (uint32_t)ell * BAND;
-                        for (uint32_t r = lane; r < BAND; r += 64) {
-                            const uint32_t row = rb + r;
-                            if (row < m) {
-                                const uint32_t c = xc[row];
-                                atomicOr((unsigned long long *)(pmw + c * WPL + r / 64), 1ull << (r % 64));
+                        if (ell < md_lo || (ell - NBD + 1 < md_lo && md_lo > band_lo)) {
+                            md_lo = ell - 63 > band_lo ? ell - 63 : band_lo;
+                            const int32_t bg = md_lo + lane;
+                            if (bg <= ell) {
+                                const uint32_t g = lane0 + (uint32_t)bg;
+                                const uint32_t it = item0 + g / 64;
+                                const uint32_t ln = g % 64;
+                                const size_t li = (size_t)it * 64 + ln;
+                                v_skew = a.ln_skew[li];
+                                v_yso = a.ln_ys[li] - v_skew;
+                                v_cko = a.it_ck[it] + ln;
+                                v_cbo = a.it_cb[it] + ln;
+                                v_tw = a.it_T[it] / 32;
                             }
                         }
-                        wave_lds_sync();
+                        skew = (uint32_t)__builtin_amdgcn_readlane((int32_t)v_skew, ell - md_lo);
+                        const int32_t d = rtop - ell;
+                        if (d >= 0 && d < nbr) {
+                            dsl = d;
+                            const int2 mt = bmeta[d];
+                            klo = __builtin_amdgcn_readfirstlane(mt.x);
+                            khi = __builtin_amdgcn_readfirstlane(mt.y);
+                        } else {
+                            klo = 0;
+                            khi = -1;
+                        }
                     }
                     const int32_t t = (j - 1) + (int32_t)skew;
                     const int32_t kt = t >> LOGK;
-                    if (kt > kt_hi || kt < kt_lo) {
-                        // recompute tiles kt-NB+1 .. kt of this band, one lane each
-                        kt_hi = kt;
-                        kt_lo = kt - (int32_t)NB + 1 < 0 ? 0 : kt - (int32_t)NB + 1;
-                        const uint32_t sbase = (uint32_t)kt_lo << LOGK;
-                        const uint32_t nsteps = (uint32_t)(kt_hi - kt_lo + 1) << LOGK;
-                        for (uint32_t u = lane; u < nsteps / 2; u += 64)
-                            ((uint32_t *)ystage)[u] =
-                                (uint32_t)ys[sbase + 2 * u] | ((uint32_t)ys[sbase + 2 * u + 1] << 16);
-                        for (uint32_t u = lane; u < nsteps / 32; u += 64) {
-                            const uint32_t w = (sbase >> 5) + u;
-                            cbstage[u] = w < Tw ? cb[(size_t)w * 64] : 0u;
-                        }
-                        wave_lds_sync();
-                        const uint32_t slot = (uint32_t)lane;
-                        if ((int32_t)slot <= kt_hi - kt_lo) {
-                            const int32_t ktl = kt_hi - (int32_t)slot;
-                            uint64_t V[WPL];
-#pragma unroll
-                            for (int q = 0; q < WPL; ++q) V[q] = ck[((size_t)ktl * WPL + q) * 64];
-                            const uint32_t e0 = (uint32_t)(ktl - kt_lo) << LOGK;
-                            uint64_t *tdst = tiles + (size_t)slot * K * WPL * 2;
-                            for (uint32_t o0 = 0; o0 < K; o0 += 32) {
-                                const uint32_t cw = cbstage[(e0 + o0) >> 5];
-#pragma unroll 2
-                                for (uint32_t o1 = 0; o1 < 32; o1 += 8) {
-                                    // eight stream values in one 16-byte read
-                                    const uint4 y8 = *(const uint4 *)(ystage + e0 + o0 + o1);
-                                    const uint32_t yw[4] = {y8.x, y8.y, y8.z, y8.w};
-                                    // all eight steps' match masks first: they depend on
-                                    // the codes only, and reading them before any tile
-                                    // write keeps each step off an LDS round trip
-                                    uint64_t Mg[8][WPL];
-#pragma unroll
-                                    for (int k = 0; k < 8; ++k) {
-                                        const uint32_t code =
-                                            ((k & 1) ? (yw[k >> 1] >> 16) : (yw[k >> 1] & 0xffffu)) >> kShift;
-#pragma unroll
-                                        for (int q = 0; q < WPL; ++q) Mg[k][q] = pmw[code * WPL + q];
-                                    }
-#pragma unroll
-                                    for (int k = 0; k < 8; ++k) {
-                                        uint32_t carry = (cw >> (31 - (o1 + k))) & 1u;
-                                        uint64_t *dst = tdst + (size_t)(o0 + o1 + k) * WPL * 2;
-#pragma unroll
-                                        for (int q = 0; q < WPL; ++q) {
-                                            const uint64_t M = Mg[k][q];
-                                            const uint64_t v = V[q];
-                                            const uint64_t U = v & M;
-                                            uint32_t c1, c2;
-                                            const uint32_t slo =
-                                                __builtin_addc((uint32_t)v, (uint32_t)U, carry, &c1);
-                                            const uint32_t shi = __builtin_addc(
-                                                (uint32_t)(v >> 32), (uint32_t)(U >> 32), c1, &c2);
-                                            carry = c2;
-                                            V[q] = ((((uint64_t)shi) << 32) | slo) | (v & ~M);
-                                            dst[q * 2] = V[q];
-                                            dst[q * 2 + 1] = M;
-                                        }
-                                    }
+                    if (kt > khi || kt < klo) {
+                        // a new round over bands ell, ell-1, ..., ell-nbr+1
+                        rtop = ell;
+                        nbr = ell - band_lo + 1;
+                        nbr = nbr < NBD ? nbr : NBD;
+                        const int32_t ns = nbr * NB;
+                        // each slot lane u < ns: band u/NB's last tile, from
+                        // the walk's column for the band it is in and from the
+                        // straight line for the bands below, then tile - u%NB
+                        int32_t kts = -1, khs = 0, kls = 0;
+                        uint64_t yoff = 0, cko = 0, cbo = 0;
+                        uint32_t tws = 0;
+                        {
+                            // the band data of each slot's band, read from the
+                            // lane holding it (all lanes take part in the reads)
+                            const int32_t d = lane / NB;
+                            int32_t src = ell - d - md_lo;
+                            src = src < 0 ? 0 : (src > 63 ? 63 : src);
+                            const uint32_t skd = (uint32_t)__shfl((int32_t)v_skew, src, 64);
+                            const uint64_t yso = ((uint64_t)(uint32_t)__shfl((int32_t)(v_yso >> 32), src, 64) << 32) |
+                                                 (uint32_t)__shfl((int32_t)v_yso, src, 64);
+                            const uint64_t ckd = ((uint64_t)(uint32_t)__shfl((int32_t)(v_cko >> 32), src, 64) << 32) |
+                                                 (uint32_t)__shfl((int32_t)v_cko, src, 64);
+                            const uint64_t cbd = ((uint64_t)(uint32_t)__shfl((int32_t)(v_cbo >> 32), src, 64) << 32) |
+                                                 (uint32_t)__shfl((int32_t)v_cbo, src, 64);
+                            const uint32_t twd = (uint32_t)__shfl((int32_t)v_tw, src, 64);
+                            if (lane < ns) {
+                                khs = kt;
+                                if (d > 0) {
+                                    // rows from here to band ell-d's top row, at
+                                    // the straight line's slope
+                                    const int64_t rows = (int64_t)i - (int64_t)(ell - d + 1) * (int64_t)BAND;
+                                    int64_t c = (int64_t)j - rows * (int64_t)n / (int64_t)m + margin;
+                                    c = c > j ? j : c;
+                                    c = c < 1 ? 1 : c;
+                                    khs = (int32_t)((c - 1 + (int64_t)skd) >> LOGK);
                                 }
+                                kls = khs - NB + 1 < 0 ? 0 : khs - NB + 1;
+                                kts = khs - lane % NB;
+                                if (kts < kls) kts = -1;
+                                yoff = yso + ((uint64_t)(kts < 0 ? 0 : kts) << LOGK);
+                                cko = ckd;
+                                cbo = cbd;
+                                tws = twd;
                             }
                         }
+                        // every global read of the round first: the rows of
+                        // the bands (match masks), the slots' checkpoints,
+                        // stream values and carry words
+                        uint64_t V0[WPL];
+#pragma unroll
+                        for (int q = 0; q < WPL; ++q)
+                            V0[q] = kts >= 0 ? a.ckpt[cko + ((size_t)kts * WPL + q) * 64] : 0ull;
+                        constexpr int kRowReads = 8;      // rows read per lane in one batch
+                        constexpr uint32_t kYPerSlot = K / 2;   // stream values per slot, in pairs
+                        const int32_t nrows = nbr * (int32_t)BAND;
+                        const int32_t nyv = ns * (int32_t)kYPerSlot;
+                        const int32_t ncb = ns * (int32_t)(K / 32);
+                        uint32_t xr[kRowReads], yv[8], cv[2];
+#pragma unroll
+                        for (int k = 0; k < kRowReads; ++k) {
+                            const int32_t r = lane + 64 * k;
+                            const uint32_t row = (uint32_t)(ell - r / (int32_t)BAND) * BAND + (uint32_t)(r % (int32_t)BAND);
+                            xr[k] = (r < nrows && row < m) ? (uint32_t)xc[row] : 0xffffffffu;
+                        }
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            const int32_t x = lane + 64 * k;
+                            const int32_t u = x / (int32_t)kYPerSlot;
+                            const uint64_t yo = ((uint64_t)(uint32_t)__shfl((int32_t)(yoff >> 32), u & 63, 64) << 32) |
+                                                (uint32_t)__shfl((int32_t)yoff, u & 63, 64);
+                            const bool ok = x < nyv && __shfl(kts, u & 63, 64) >= 0;
+                            const uint16_t *ysrc = a.ystream + yo + 2 * (uint32_t)(x % (int32_t)kYPerSlot);
+                            yv[k] = ok ? ((uint32_t)ysrc[0] | ((uint32_t)ysrc[1] << 16)) : 0u;
+                        }
+#pragma unroll
+                        for (int k = 0; k < 2; ++k) {
+                            const int32_t x = lane + 64 * k;
+                            const int32_t u = x / (int32_t)(K / 32);
+                            const uint64_t cb0 = ((uint64_t)(uint32_t)__shfl((int32_t)(cbo >> 32), u & 63, 64) << 32) |
+                                                 (uint32_t)__shfl((int32_t)cbo, u & 63, 64);
+                            const int32_t ku = __shfl(kts, u & 63, 64);
+                            const uint32_t tw = (uint32_t)__shfl((int32_t)tws, u & 63, 64);
+                            const uint32_t w = ((uint32_t)ku << (LOGK - 5)) + (uint32_t)(x % (int32_t)(K / 32));
+                            cv[k] = (x < ncb && ku >= 0 && w < tw) ? a.cbits[cb0 + (size_t)w * 64] : 0u;
+                        }
+                        // match masks of the round's bands
+                        for (int32_t u = lane; u < nbr * sig1 * WPL; u += 64) pm[u] = 0;
+                        if (lane < ns && lane % NB == 0) bmeta[lane / NB] = make_int2(kls, khs);
                         wave_lds_sync();
+#pragma unroll
+                        for (int k = 0; k < kRowReads; ++k) {
+                            const int32_t r = lane + 64 * k;
+                            if (xr[k] != 0xffffffffu) {
+                                const int32_t rr = r % (int32_t)BAND;
+                                atomicOr((unsigned long long *)(pm + ((size_t)(r / (int32_t)BAND) * sig1 + xr[k]) * WPL + rr / 64),
+                                         1ull << (rr % 64));
+                            }
+                        }
+                        for (int32_t r0 = 64 * kRowReads; r0 < nrows; r0 += 64) {
+                            // rounds with more rows than one batch of reads
+                            const int32_t r = r0 + lane;
+                            const uint32_t row = (uint32_t)(ell - r / (int32_t)BAND) * BAND + (uint32_t)(r % (int32_t)BAND);
+                            if (r < nrows && row < m) {
+                                const int32_t rr = r % (int32_t)BAND;
+                                atomicOr((unsigned long long *)(pm + ((size_t)(r / (int32_t)BAND) * sig1 + xc[row]) * WPL + rr / 64),
+                                         1ull << (rr % 64));
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            const int32_t x = lane + 64 * k;
+                            if (x < nyv) ((uint32_t *)ystage)[x] = yv[k];
+                        }
+                        for (int32_t x0 = 64 * 8; x0 < nyv; x0 += 64) {
+                            // (uniform trip count: every lane takes part in the reads)
+                            const int32_t x = x0 + lane;
+                            const int32_t u = x / (int32_t)kYPerSlot;
+                            const uint64_t yo = ((uint64_t)(uint32_t)__shfl((int32_t)(yoff >> 32), u & 63, 64) << 32) |
+                                                (uint32_t)__shfl((int32_t)yoff, u & 63, 64);
+                            const bool ok = x < nyv && __shfl(kts, u & 63, 64) >= 0;
+                            if (ok) {
+                                const uint16_t *ysrc = a.ystream + yo + 2 * (uint32_t)(x % (int32_t)kYPerSlot);
+                                ((uint32_t *)ystage)[x] = (uint32_t)ysrc[0] | ((uint32_t)ysrc[1] << 16);
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < 2; ++k) {
+                            const int32_t x = lane + 64 * k;
+                            if (x < ncb) cbstage[x] = cv[k];
+                        }
+                        for (int32_t x0 = 64 * 2; x0 < ncb; x0 += 64) {
+                            const int32_t x = x0 + lane;
+                            const int32_t u = x / (int32_t)(K / 32);
+                            const uint64_t cb0 = ((uint64_t)(uint32_t)__shfl((int32_t)(cbo >> 32), u & 63, 64) << 32) |
+                                                 (uint32_t)__shfl((int32_t)cbo, u & 63, 64);
+                            const int32_t ku = __shfl(kts, u & 63, 64);
+                            const uint32_t tw = (uint32_t)__shfl((int32_t)tws, u & 63, 64);
+                            const uint32_t w = ((uint32_t)ku << (LOGK - 5)) + (uint32_t)(x % (int32_t)(K / 32));
+                            if (x < ncb) cbstage[x] = (ku >= 0 && w < tw) ? a.cbits[cb0 + (size_t)w * 64] : 0u;
+                        }
+                        wave_lds_sync();
+                        if (kts >= 0)
+                            recompute_tile<WPL, LOGK>(tiles + (size_t)lane * SW,
+                                                      pm + (size_t)(lane / NB) * sig1 * WPL,
+                                                      ystage + (size_t)lane * K,
+                                                      cbstage + (size_t)lane * (K / 32), V0);
+                        wave_lds_sync();
+                        dsl = 0;
+                        khi = kt;
+                        klo = kt - NB + 1 < 0 ? 0 : kt - NB + 1;
                     }
                     // walk inside the resident tiles of this band.  A window holds
-                    // word q of 64 consecutive columns in lane registers, lane l
-                    // holding column tc - l.  A diagonal step at row b of column k
-                    // happens exactly when the match bit M_k[b] is set (a set match
-                    // bit is the highest candidate at or below b), so a run of
-                    // diagonal steps is found at once: lane l tests bit b - (l - k)
-                    // of its match word and the run is the count of consecutive set
-                    // ballot bits from lane k.  Other steps take the top candidate
-                    // bit of PM[y_j] | ~V_j at or below b.  Every bitmap word the
-                    // walk passes through is written whole.
+                    // word q of up to 64 consecutive columns in lane registers,
+                    // lane l holding column tc - l.  A diagonal step at row b of
+                    // column k happens exactly when the match bit M_k[b] is set (a
+                    // set match bit is the highest candidate at or below b), so a
+                    // run of diagonal steps is found at once: it is the number of
+                    // consecutive lanes l >= k with bit b - (l - k) of M_l set,
+                    // i.e. with bit b + k of the 128-bit value M_l << l set.  The
+                    // step after a run takes the top candidate bit of
+                    // PM[y_j] | ~V_j at or below b.  Every bitmap word the walk
+                    // passes through is written whole.
                     const int32_t rbase = ell * (int32_t)BAND;
-                    const int32_t tfloor = kt_lo << LOGK;     // first resident step
+                    const int32_t tfloor = klo << LOGK;       // first resident step
+                    const uint64_t *pmd = pm + (size_t)dsl * sig1 * WPL;
                     int32_t tc = t;
                     int32_t q = (i - 1 - rbase) >> 6;
                     int32_t b = (i - 1 - rbase) & 63;
@@ -646,55 +806,40 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
                         const int32_t tl = tc - lane;
                         uint64_t VL = 0, ML = 0;
                         if (tl >= tfloor) {
-                            const uint32_t sl = (uint32_t)(kt_hi - (tl >> LOGK));
-                            const uint64_t *tp =
-                                tiles + (((size_t)sl << LOGK) + ((uint32_t)tl & (K - 1))) * WPL * 2 + q * 2;
-                            VL = tp[0];
-                            ML = tp[1];
+                            const uint32_t sl = (uint32_t)(dsl * NB + (khi - (tl >> LOGK)));
+                            const uint32_t o = (uint32_t)tl & (K - 1);
+                            VL = tiles[(size_t)sl * SW + o * WPL + q];
+                            const uint32_t code = (uint32_t)ystage[(size_t)sl * K + o] >> kShift;
+                            ML = pmd[code * WPL + q];
                         }
                         if (wq0 + q != dwi) {
                             if (dwi >= 0 && lane == 0) dg[dwi] = dword;
                             dwi = wq0 + q;
                             dword = 0;
                         }
+                        const uint64_t Slo = ML << lane;
+                        const uint64_t Shi = lane ? ML >> (64 - lane) : 0ull;
                         const int32_t avail = tc - tfloor + 1;    // columns resident from tc down
                         int32_t kmax = avail < 64 ? avail : 64;
                         kmax = kmax < j ? kmax : j;
+                        const uint64_t wmask = kmax >= 64 ? ~0ull : ((1ull << kmax) - 1);
                         int32_t k = 0;
-                        while (k < kmax) {
+                        for (;;) {
                             // diagonal run from (b, k)
-                            const int32_t sh = b + k - lane;
-                            const bool bit = lane >= k && lane < kmax && sh >= 0 && ((ML >> (sh & 63)) & 1ull);
-                            const uint64_t dm = __builtin_amdgcn_ballot_w64(bit) >> k;
-                            const uint64_t nz = ~dm;
-                            const int32_t run = nz ? (int32_t)__builtin_ctzll(nz) : 64;
-                            if (run > 0) {
-                                const uint64_t ones = run >= 64 ? ~0ull : ((1ull << run) - 1);
-                                dword |= ones << (b - run + 1);
-                                b -= run;
-                                k += run;
-                                if (b < 0) {
-                                    if (q == 0) { leave = true; break; }   // out of the band, downward
-                                    if (lane == 0) dg[dwi] = dword;
-                                    --q;
-                                    --dwi;
-                                    dword = 0;
-                                    b = 63;
-                                    break;
-                                }
-                                continue;
-                            }
-                            // one general step at column k
+                            const int32_t pl = b + k;
+                            const uint64_t xs = pl < 64 ? Slo : Shi;
+                            const bool bit = ((uint32_t)(xs >> (pl & 63)) & 1u) != 0;
+                            const uint64_t dm = (__builtin_amdgcn_ballot_w64(bit) & wmask) >> k;
+                            const int32_t run = ~dm ? (int32_t)__builtin_ctzll(~dm) : 64;
+                            dword |= (run >= 64 ? ~0ull : ((1ull << run) - 1)) << (b - run + 1);
+                            b -= run;
+                            k += run;
+                            if (b < 0 || k >= kmax) break;
+                            // one general step at column k (M_k[b] is clear)
                             const uint64_t Vw = readlane64(VL, k), Mw = readlane64(ML, k);
                             const uint64_t cand = (Mw | ~Vw) & (~0ull >> (63 - b));
                             if (cand == 0) {
-                                // up through the rest of word q in this column
-                                if (q == 0) { b = -1; leave = true; break; }
-                                if (lane == 0) dg[dwi] = dword;
-                                --q;
-                                --dwi;
-                                dword = 0;
-                                b = 63;
+                                b = -1;       // climbs out of word q in column k
                                 break;
                             }
                             const int32_t r = 63 - (int32_t)__builtin_clzll(cand);
@@ -702,18 +847,22 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
                             dword |= (uint64_t)d << r;
                             b = r - (int32_t)d;
                             ++k;
-                            if (b < 0) {
-                                if (q == 0) { leave = true; break; }
+                            if (b < 0 || k >= kmax) break;
+                        }
+                        j -= k;
+                        tc -= k;
+                        if (b < 0) {
+                            // on to row 63 of word q-1 in column j, or out of the band
+                            if (q == 0) {
+                                leave = true;
+                            } else {
                                 if (lane == 0) dg[dwi] = dword;
                                 --q;
                                 --dwi;
                                 dword = 0;
                                 b = 63;
-                                break;
                             }
                         }
-                        j -= k;
-                        tc -= k;
                         if (j == 0 || tc < tfloor) leave = true;
                     }
                     i = rbase + q * 64 + b + 1;
@@ -774,7 +923,15 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
         uint64_t base = 0;
         for (uint32_t w0 = 0; w0 < W; w0 += 64) {
             const uint32_t w = w0 + lane;
-            uint64_t bits = w < W ? bm[w] : 0ull;
+            uint64_t bits = 0;
+            uint4 xv[4] = {};
+            if (w < W) {
+                // the word's 64 symbols at once (X is padded to whole words)
+                bits = bm[w];
+                const uint4 *xs = (const uint4 *)(x + (size_t)w * 64);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) xv[k] = xs[k];
+            }
             const uint32_t c = (uint32_t)__builtin_popcountll(bits);
             uint32_t incl = c;
 #pragma unroll
@@ -784,11 +941,19 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
             }
             const uint32_t total = __shfl(incl, 63, 64);
             uint64_t pos = base + incl - c;
-            while (bits) {
-                const int r = __builtin_ctzll(bits);
-                if (pos < cap) o[pos] = x[(size_t)w * 64 + r];
-                ++pos;
-                bits &= bits - 1;
+            const uint32_t xw[16] = {xv[0].x, xv[0].y, xv[0].z, xv[0].w, xv[1].x, xv[1].y,
+                                     xv[1].z, xv[1].w, xv[2].x, xv[2].y, xv[2].z, xv[2].w,
+                                     xv[3].x, xv[3].y, xv[3].z, xv[3].w};
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                // rows 4k+1 .. 4k+4 of the word
+                uint32_t mk = (uint32_t)(bits >> (4 * k)) & 0xfu;
+                while (mk) {
+                    const int r = __builtin_ctz(mk);
+                    if (pos < cap) o[pos] = (uint8_t)(xw[k] >> (8 * r));
+                    ++pos;
+                    mk &= mk - 1;
+                }
             }
             base += total;
         }
@@ -821,7 +986,7 @@ const void *tb_symbol(int wpl, int ckpt_every) {
 
 hipError_t launch_tb(int wpl, const TbArgs &a, uint32_t grid, hipStream_t s) {
     if (a.ckpt_every != 64 && a.ckpt_every != 128 && a.ckpt_every != 256) return hipErrorInvalidValue;
-    const size_t lds = tb_lds_bytes(wpl, a.sigma, a.ckpt_every, a.nb);
+    const size_t lds = tb_lds_bytes(wpl, a.sigma, a.ckpt_every, a.nb, a.nbands);
     const int logk = a.ckpt_every == 64 ? 6 : a.ckpt_every == 128 ? 7 : 8;
 #define LCS_TB_LAUNCH(W, L)                                                               \
     if (wpl == W && logk == L) {                                                          \
