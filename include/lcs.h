@@ -86,18 +86,18 @@ typedef struct lcs_batch lcs_batch;
  *  words_per_lane  : 64-bit words of the bit-vector column held per lane
  *                    (1, 2, 4 or 8);
  *  ckpt_interval   : columns between stored bit-vector checkpoints for the
- *                    traceback (64, 128 or 256);
+ *                    traceback (64, 128 or 256; default 64);
  *  persistent_waves: cap on resident work-groups of the persistent kernels;
  *  plain           : 1 = no packing: one pair per work-group and one launch
  *                    per pair (the plain per-pair path, for comparison);
  *  strip_rows      : rows per traceback strip (rounded up to a multiple of
- *                    64*words_per_lane; default 2048).  The walk of a pair is
+ *                    64*words_per_lane; default 4096).  The walk of a pair is
  *                    split into strips walked in parallel from estimated
  *                    entry columns and then reconciled; the result does not
  *                    depend on this value;
  *  tb_tiles        : checkpoint intervals per band the traceback
- *                    recomputes at once (1..8, default 2, or 1 for wide
- *                    bands);
+ *                    recomputes at once (1..8; default: about 256 columns
+ *                    worth, fewer for wide bands);
  *  tb_bands        : bands the traceback recomputes at once (1..16,
  *                    tb_tiles * tb_bands <= 64; default: as many, up to 4,
  *                    as fit about 10 KiB of LDS per wave). */

@@ -103,7 +103,8 @@ struct TbArgs {
 // sequential seal per pair.
 enum : int32_t { kTbSpec = 0, kTbFix = 1, kTbSeal = 2 };
 
-// Emit: bitmap of diagonal rows -> LCS bytes (X symbols in row order).
+// Emit: bitmap of diagonal rows -> LCS bytes (X symbols in row order), one
+// item per 64 bitmap words of a pair.
 struct EmitArgs {
     const uint8_t *xbytes;
     const uint64_t *pair_xoff;
@@ -114,7 +115,9 @@ struct EmitArgs {
     const uint64_t *pair_out;
     const uint64_t *out_len;
     uint8_t *out;
-    uint32_t npairs;
+    const uint32_t *em_pair;    // per item: pair
+    const uint32_t *em_w0;      // per item: first of its (up to) 64 bitmap words
+    uint32_t nitems;
     uint32_t *error;            // set to 2 when a bitmap disagrees with the length
 };
 

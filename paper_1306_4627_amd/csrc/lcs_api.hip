@@ -100,6 +100,9 @@ struct lcs_batch {
     uint64_t *pair_xoff = nullptr, *pair_yoff = nullptr, *pair_out = nullptr, *out_len = nullptr;
     uint64_t *pair_diag = nullptr, *diag = nullptr;   // diag lives in zero64
     uint64_t diag_words = 0;
+    // emit items: (pair, first bitmap word) per 64 bitmap words, pair order
+    std::vector<uint32_t> em_pair_host, em_w0_host, em_first_host;
+    uint32_t *em_pair = nullptr, *em_w0 = nullptr;
     std::vector<uint64_t> diag_off_host;
     uint32_t *pair_m = nullptr, *pair_n = nullptr;
     uint64_t *seg_yoff = nullptr, *seg_begin = nullptr, *seg_len = nullptr;
@@ -199,10 +202,10 @@ static lcs_status check_tuning(const lcs_tuning *t) {
 static void fill_plan_config(PlanConfig &cfg, int sigma, uint32_t flags, const lcs_tuning *t) {
     cfg.wpl = t ? t->words_per_lane : 0;
     cfg.traceback = (flags & LCS_WANT_TRACEBACK) != 0;
-    cfg.ckpt = (t && t->ckpt_interval) ? t->ckpt_interval : 128;
+    cfg.ckpt = (t && t->ckpt_interval) ? t->ckpt_interval : 64;
     cfg.sigma = sigma;
     cfg.plain = t && t->plain;
-    cfg.strip_rows = (t && t->strip_rows) ? t->strip_rows : 2048;
+    cfg.strip_rows = (t && t->strip_rows) ? t->strip_rows : 4096;
 }
 
 static void stats_from_plan(const Plan &p, uint64_t npairs, lcs_batch_stats *out) {
@@ -341,6 +344,8 @@ static size_t carve(lcs_batch *b, char *base) {
     b->pair_out = cv.take<uint64_t>(np + 1);
     b->out_len = cv.take<uint64_t>(np + 1);
     b->pair_diag = cv.take<uint64_t>(np + 1);
+    b->em_pair = cv.take<uint32_t>(b->em_pair_host.size() + 1);
+    b->em_w0 = cv.take<uint32_t>(b->em_w0_host.size() + 1);
     b->pair_m = cv.take<uint32_t>(np + 1);
     b->pair_n = cv.take<uint32_t>(np + 1);
     const size_t ns = p.segs.size();
@@ -483,6 +488,16 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
             dw += (pairs[k].m + 63) / 64;
         }
         b->diag_words = dw;
+        b->em_first_host.assign(count + 1, 0);
+        for (uint64_t k = 0; k < count; ++k) {
+            b->em_first_host[k] = (uint32_t)b->em_pair_host.size();
+            const uint64_t W = (pairs[k].m + 63) / 64;
+            for (uint64_t w0 = 0; w0 < W; w0 += 64) {
+                b->em_pair_host.push_back((uint32_t)k);
+                b->em_w0_host.push_back((uint32_t)w0);
+            }
+        }
+        b->em_first_host[count] = (uint32_t)b->em_pair_host.size();
     }
     b->xarena = xa;
     b->yarena = ya;
@@ -559,6 +574,8 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     UP(bp->pair_yoff, yoff.data(), count * 8);
     UP(bp->pair_out, bp->out_off_host.data(), count * 8);
     UP(bp->pair_diag, bp->diag_off_host.data(), count * 8);
+    UP(bp->em_pair, bp->em_pair_host.data(), bp->em_pair_host.size() * 4);
+    UP(bp->em_w0, bp->em_w0_host.data(), bp->em_w0_host.size() * 4);
     UP(bp->pair_m, hm.data(), count * 4);
     UP(bp->pair_n, hn.data(), count * 4);
     UP(bp->seg_yoff, s_yoff.data(), ns * 8);
@@ -600,12 +617,15 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
             for (uint32_t T : C.it_T) mt = std::max(mt, T);
             D.prio_T = std::max<uint32_t>(mt / 2, 1);
         }
-        // traceback recompute rounds: by default two tiles per band and as
-        // many bands (up to four) as fit about 10 KiB of LDS per wave (more
-        // LDS per wave costs more in resident waves than it saves in rounds)
+        // traceback recompute rounds: by default tiles spanning about 256
+        // columns per band and as many bands (up to four) as fit about 10 KiB
+        // of LDS per wave (more LDS per wave costs more in resident waves than
+        // it saves in rounds)
         {
             const size_t slot = tb_lds_bytes(C.wpl, sigma, cfg.ckpt, 1, 1) / (kTbBlock / 64);
-            D.nb = (tuning && tuning->tb_tiles) ? tuning->tb_tiles : (slot > 6 * 1024 ? 1 : 2);
+            const int span = std::max(1, 256 / cfg.ckpt);
+            const int room = std::max(1, (int)((10 * 1024) / slot));
+            D.nb = (tuning && tuning->tb_tiles) ? tuning->tb_tiles : std::min(span, room);
             const int fit = (int)((10 * 1024) / (slot * D.nb));
             D.nbands = (tuning && tuning->tb_bands) ? tuning->tb_bands : std::max(1, std::min(4, fit));
             if (D.nb * D.nbands > 64 ||
@@ -778,7 +798,9 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
     ea.pair_out = b->pair_out;
     ea.out_len = b->out_len;
     ea.out = b->out;
-    ea.npairs = (uint32_t)b->npairs;
+    ea.em_pair = b->em_pair;
+    ea.em_w0 = b->em_w0;
+    ea.nitems = (uint32_t)b->em_pair_host.size();
     ea.error = b->error;
     if (!b->plain) {
         for (size_t ci = 0; ci < b->cls.size(); ++ci) {
@@ -835,13 +857,9 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
                     }
                     const uint32_t pr = D.pl_pair[k];
                     EmitArgs e1 = ea;
-                    e1.pair_xoff += pr;
-                    e1.pair_m += pr;
-                    e1.pair_n += pr;
-                    e1.pair_diag += pr;
-                    e1.pair_out += pr;
-                    e1.out_len += pr;
-                    e1.npairs = 1;
+                    e1.em_pair += b->em_first_host[pr];
+                    e1.em_w0 += b->em_first_host[pr];
+                    e1.nitems = b->em_first_host[pr + 1] - b->em_first_host[pr];
                     HIP_TRY(launch_emit(e1, s));
                 }
             }

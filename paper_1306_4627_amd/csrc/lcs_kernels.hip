@@ -55,7 +55,14 @@ __global__ void k_remap_x(const uint8_t *__restrict__ lut, const uint8_t *__rest
 // One work-group per stream region (grid-stride over regions): codes of Y at
 // columns 0..n-1, the sentinel code everywhere else in the region, each
 // shifted into a byte offset of its row of match masks.
-__global__ void k_streams(PrepArgs a) {
+__global__ __launch_bounds__(256) void k_streams(PrepArgs a) {
+    // the byte -> code table in LDS; each thread writes eight stream values
+    // (16 bytes, aligned: regions start at multiples of 64 elements and are
+    // padded to them) per pass, and gridDim.y blocks share a region
+    __shared__ uint8_t lut[256];
+    lut[threadIdx.x] = a.lut[threadIdx.x];
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.y * blockDim.x * 8;
     for (uint32_t s = blockIdx.x; s < a.nseg; s += gridDim.x) {
         const uint64_t begin = a.seg_begin[s];
         const uint64_t len = a.seg_len[s];
@@ -63,11 +70,34 @@ __global__ void k_streams(PrepArgs a) {
         const uint64_t n = a.seg_n[s];
         const uint32_t sh = a.seg_shift[s];
         const uint8_t *y = a.ybytes + a.seg_yoff[s];
-        const uint16_t sent = (uint16_t)(a.sentinel << sh);
-        for (uint64_t k = threadIdx.x; k < len; k += blockDim.x) {
-            uint16_t c = sent;
-            if (k >= pre && k - pre < n) c = (uint16_t)((uint32_t)a.lut[y[k - pre]] << sh);
-            a.ystream[begin + k] = c;
+        const uint32_t sent = (uint32_t)a.sentinel << sh;
+        for (uint64_t k0 = ((uint64_t)blockIdx.y * blockDim.x + threadIdx.x) * 8; k0 < len; k0 += stride) {
+            uint32_t c[8];
+            if (k0 >= pre && k0 + 8 <= pre + n) {
+                // eight bytes of Y from two aligned 8-byte reads (the Y arena
+                // is padded by 64 bytes)
+                const uintptr_t ad = (uintptr_t)(y + (k0 - pre));
+                const uint64_t *al = (const uint64_t *)(ad & ~(uintptr_t)7);
+                const uint32_t s8 = (uint32_t)(ad & 7) * 8;
+                const uint64_t lo = al[0], hi = al[1];
+                const uint64_t v = s8 ? (lo >> s8) | (hi << (64 - s8)) : lo;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) c[e] = (uint32_t)(v >> (8 * e)) & 0xffu;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint64_t k = k0 + e;
+                    c[e] = (k >= pre && k - pre < n) ? (uint32_t)y[k - pre] : 0x100u;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) c[e] = c[e] == 0x100u ? sent : ((uint32_t)lut[c[e]] << sh);
+            uint4 v;
+            v.x = c[0] | (c[1] << 16);
+            v.y = c[2] | (c[3] << 16);
+            v.z = c[4] | (c[5] << 16);
+            v.w = c[6] | (c[7] << 16);
+            *(uint4 *)(a.ystream + begin + k0) = v;
         }
     }
 }
@@ -90,7 +120,7 @@ hipError_t launch_prep(const PrepArgs &a, uint64_t xbytes_n, hipStream_t s) {
     hipLaunchKernelGGL(k_zero, dim3(512), dim3(256), 0, s, a);
     if (a.nseg) {
         uint32_t blocks = a.nseg < 65536 ? a.nseg : 65536;
-        hipLaunchKernelGGL(k_streams, dim3(blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_streams, dim3(blocks, 8), dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -906,13 +936,22 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
     }
 }
 
-// One wave per pair: the bitmap of diagonal rows, read in row order, selects
-// the symbols of X that form the LCS.
+// The bitmap of diagonal rows, read in row order, selects the symbols of X
+// that form the LCS.  One wave per item of 64 bitmap words of a pair: the
+// item's output starts at the number of set bits in the words before it;
+// each lane places the symbols of its word in an LDS staging buffer at its
+// prefix-sum offset, and the wave then writes the buffer out with
+// consecutive lanes on consecutive bytes.  The item holding a pair's last
+// word checks the pair's total against its length.
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
+    __shared__ uint8_t stage_all[4][64 * 64];
     const int lane = threadIdx.x & 63;
+    uint8_t *stage = stage_all[threadIdx.x >> 6];
     const uint32_t waves = gridDim.x * (blockDim.x / 64);
-    for (uint32_t p = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); p < a.npairs;
-         p += waves) {
+    for (uint32_t it = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); it < a.nitems;
+         it += waves) {
+        const uint32_t p = a.em_pair[it];
+        const uint32_t w0 = a.em_w0[it];
         const uint32_t m = a.pair_m[p];
         const uint32_t n = a.pair_n[p];
         const uint64_t cap = m < n ? m : n;     // the pair's slot in `out`
@@ -920,51 +959,55 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
         const uint64_t *bm = a.diag + a.pair_diag[p];
         const uint8_t *x = a.xbytes + a.pair_xoff[p];
         uint8_t *o = a.out + a.pair_out[p];
-        uint64_t base = 0;
-        for (uint32_t w0 = 0; w0 < W; w0 += 64) {
-            const uint32_t w = w0 + lane;
-            uint64_t bits = 0;
-            uint4 xv[4] = {};
-            if (w < W) {
-                // the word's 64 symbols at once (X is padded to whole words)
-                bits = bm[w];
-                const uint4 *xs = (const uint4 *)(x + (size_t)w * 64);
+        uint32_t before = 0;
+        for (uint32_t v = lane; v < w0; v += 64) before += (uint32_t)__builtin_popcountll(bm[v]);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) xv[k] = xs[k];
-            }
-            const uint32_t c = (uint32_t)__builtin_popcountll(bits);
-            uint32_t incl = c;
+        for (int d = 32; d >= 1; d >>= 1) before += __shfl_xor(before, d, 64);
+        const uint32_t w = w0 + lane;
+        uint64_t bits = 0;
+        uint4 xv[4] = {};
+        if (w < W) {
+            // the word's 64 symbols at once (X is padded to whole words)
+            bits = bm[w];
+            const uint4 *xs = (const uint4 *)(x + (size_t)w * 64);
 #pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint32_t up = __shfl_up(incl, d, 64);
-                if (lane >= d) incl += up;
-            }
-            const uint32_t total = __shfl(incl, 63, 64);
-            uint64_t pos = base + incl - c;
-            const uint32_t xw[16] = {xv[0].x, xv[0].y, xv[0].z, xv[0].w, xv[1].x, xv[1].y,
-                                     xv[1].z, xv[1].w, xv[2].x, xv[2].y, xv[2].z, xv[2].w,
-                                     xv[3].x, xv[3].y, xv[3].z, xv[3].w};
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                // rows 4k+1 .. 4k+4 of the word
-                uint32_t mk = (uint32_t)(bits >> (4 * k)) & 0xfu;
-                while (mk) {
-                    const int r = __builtin_ctz(mk);
-                    if (pos < cap) o[pos] = (uint8_t)(xw[k] >> (8 * r));
-                    ++pos;
-                    mk &= mk - 1;
-                }
-            }
-            base += total;
+            for (int k = 0; k < 4; ++k) xv[k] = xs[k];
         }
-        if (lane == 0 && base != a.out_len[p]) atomicOr(a.error, 2u);
+        const uint32_t c = (uint32_t)__builtin_popcountll(bits);
+        uint32_t incl = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t up = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += up;
+        }
+        const uint32_t total = __shfl(incl, 63, 64);
+        uint32_t pos = incl - c;
+        const uint32_t xw[16] = {xv[0].x, xv[0].y, xv[0].z, xv[0].w, xv[1].x, xv[1].y,
+                                 xv[1].z, xv[1].w, xv[2].x, xv[2].y, xv[2].z, xv[2].w,
+                                 xv[3].x, xv[3].y, xv[3].z, xv[3].w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            // rows 4k+1 .. 4k+4 of the word
+            uint32_t mk = (uint32_t)(bits >> (4 * k)) & 0xfu;
+            while (mk) {
+                const int r = __builtin_ctz(mk);
+                stage[pos++] = (uint8_t)(xw[k] >> (8 * r));
+                mk &= mk - 1;
+            }
+        }
+        wave_lds_sync();
+        const uint64_t base = before;
+        for (uint32_t e = lane; e < total; e += 64)
+            if (base + e < cap) o[base + e] = stage[e];
+        wave_lds_sync();
+        if (lane == 0 && w0 + 64 >= W && base + total != a.out_len[p]) atomicOr(a.error, 2u);
     }
 }
 
 hipError_t launch_emit(const EmitArgs &a, hipStream_t s) {
-    if (!a.npairs) return hipSuccess;
-    uint32_t blocks = (a.npairs + 3) / 4;
-    if (blocks > 8192) blocks = 8192;
+    if (!a.nitems) return hipSuccess;
+    uint32_t blocks = (a.nitems + 3) / 4;
+    if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -40,10 +40,10 @@ struct PairShape {
 struct PlanConfig {
     int wpl = 4;            // words per lane (1, 2, 4, 8)
     bool traceback = false;
-    int ckpt = 128;         // steps between stored V checkpoints (multiple of kChunk)
+    int ckpt = 64;          // steps between stored V checkpoints (multiple of kChunk)
     int sigma = 4;          // alphabet size; code sigma is the zero-mask sentinel
     bool plain = false;     // one pair per item, no packing
-    int strip_rows = 2048;  // rows per traceback strip (rounded up to whole bands)
+    int strip_rows = 4096;  // rows per traceback strip (rounded up to whole bands)
 };
 
 // One class = one fill launch with a fixed words-per-lane.
