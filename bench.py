@@ -65,7 +65,7 @@ def measured_traffic(workload: str):
     """HBM bytes per fill launch from the committed rocprofv3 counter runs,
     or None when they were taken on a different kernel source or workload."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1306_4627_amd", "csrc", "lcs_kernels.hip")
+    src = os.path.join(ROOT, "paper_1306_4627_amd", "csrc", "fill.hip")
     rec_file = os.path.join(ROOT, "profiles", "k_fill_batch_related_4096.md")
     try:
         h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]

@@ -1,25 +1,4 @@
-// lcs_kernels.hip -- gfx950 kernels of the LCS library.
-//
-// Bit-vector form of the dynamic program of section I.C.  For column j let
-// V_j be the m-bit vector whose bit (i-1) is 1 exactly when
-// c[i][j] == c[i-1][j].  Column 0 is all zero in c, so V_0 is all ones; with
-// PM_a the match mask of symbol a (bit (i-1) set when x_i == a), one column
-// step is the add-and-mask recurrence of Allison & Dix (1986) in the
-// four-operation form of Crochemore, Iliopoulos, Pinzon & Reid (2001):
-//
-//     U = V & PM[y_j]        V' = (V + U) | (V & ~PM[y_j])
-//
-// where "+" is an m-bit addition whose carries run from row 1 upward.  Then
-// c[i][j] = i - popcount(V_j & (2^i - 1)), so the LCS length c[m][n] is the
-// number of zero bits among the m valid bits of V_n.
-//
-// Mapping: a lane keeps WPL consecutive 64-bit words of V in registers; a
-// pair's words are spread over consecutive lanes.  Lane k of a pair works on
-// column (t - skew_k) at step t with skew growing by one per lane, so the
-// carry leaving lane k-1 for column j is produced one step before lane k
-// needs it: the carry hand-over is a shift of the wave's carry-out lane mask
-// (ballot) by one lane, fed back as the carry-in lane mask of the next step.
-// No cross-lane add is ever waited for inside a step.
+// traceback.hip -- the canonical traceback and the emit of the LCS bytes.
 //
 // Traceback (section I.D with ties going up): at (i, j) a match moves
 // diagonally and emits x_i; otherwise c[i-1][j] >= c[i][j-1] holds exactly
@@ -30,414 +9,9 @@
 // (lane, step range) tile of the V history can be recomputed on its own;
 // the traceback recomputes only the tiles the path crosses.
 #include "kernels.hpp"
+#include "bitvec.hpp"
 
 namespace lcs {
-
-// --------------------------------------------------------------------------
-// prep: symbol remap (bytes -> codes), Y streams, zeroing
-// --------------------------------------------------------------------------
-
-__global__ void k_remap_x(const uint8_t *__restrict__ lut, const uint8_t *__restrict__ src,
-                          uint8_t *__restrict__ dst, uint64_t n) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 4;
-    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i < n; i += stride) {
-        if (i + 4 <= n) {
-            uint32_t w = *(const uint32_t *)(src + i);
-            uint32_t r = (uint32_t)lut[w & 0xff] | ((uint32_t)lut[(w >> 8) & 0xff] << 8) |
-                         ((uint32_t)lut[(w >> 16) & 0xff] << 16) | ((uint32_t)lut[w >> 24] << 24);
-            *(uint32_t *)(dst + i) = r;
-        } else {
-            for (uint64_t k = i; k < n; ++k) dst[k] = lut[src[k]];
-        }
-    }
-}
-
-// One work-group per stream region (grid-stride over regions): codes of Y at
-// columns 0..n-1, the sentinel code everywhere else in the region, each
-// shifted into a byte offset of its row of match masks.
-__global__ __launch_bounds__(256) void k_streams(PrepArgs a) {
-    // the byte -> code table in LDS; each thread writes eight stream values
-    // (16 bytes, aligned: regions start at multiples of 64 elements and are
-    // padded to them) per pass, and gridDim.y blocks share a region
-    __shared__ uint8_t lut[256];
-    lut[threadIdx.x] = a.lut[threadIdx.x];
-    __syncthreads();
-    const uint64_t stride = (uint64_t)gridDim.y * blockDim.x * 8;
-    for (uint32_t s = blockIdx.x; s < a.nseg; s += gridDim.x) {
-        const uint64_t begin = a.seg_begin[s];
-        const uint64_t len = a.seg_len[s];
-        const uint64_t pre = a.seg_pre[s];
-        const uint64_t n = a.seg_n[s];
-        const uint32_t sh = a.seg_shift[s];
-        const uint8_t *y = a.ybytes + a.seg_yoff[s];
-        const uint32_t sent = (uint32_t)a.sentinel << sh;
-        for (uint64_t k0 = ((uint64_t)blockIdx.y * blockDim.x + threadIdx.x) * 8; k0 < len; k0 += stride) {
-            uint32_t c[8];
-            if (k0 >= pre && k0 + 8 <= pre + n) {
-                // eight bytes of Y from two aligned 8-byte reads (the Y arena
-                // is padded by 64 bytes)
-                const uintptr_t ad = (uintptr_t)(y + (k0 - pre));
-                const uint64_t *al = (const uint64_t *)(ad & ~(uintptr_t)7);
-                const uint32_t s8 = (uint32_t)(ad & 7) * 8;
-                const uint64_t lo = al[0], hi = al[1];
-                const uint64_t v = s8 ? (lo >> s8) | (hi << (64 - s8)) : lo;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) c[e] = (uint32_t)(v >> (8 * e)) & 0xffu;
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const uint64_t k = k0 + e;
-                    c[e] = (k >= pre && k - pre < n) ? (uint32_t)y[k - pre] : 0x100u;
-                }
-            }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) c[e] = c[e] == 0x100u ? sent : ((uint32_t)lut[c[e]] << sh);
-            uint4 v;
-            v.x = c[0] | (c[1] << 16);
-            v.y = c[2] | (c[3] << 16);
-            v.z = c[4] | (c[5] << 16);
-            v.w = c[6] | (c[7] << 16);
-            *(uint4 *)(a.ystream + begin + k0) = v;
-        }
-    }
-}
-
-__global__ void k_zero(PrepArgs a) {
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t k = tid; k < a.npairs; k += stride) a.out_len[k] = 0;
-    for (uint64_t k = tid; k < a.nzero; k += stride) a.zero_words[k] = 0;
-    for (uint64_t k = tid; k < a.nzero64; k += stride) a.zero64[k] = 0;
-}
-
-hipError_t launch_prep(const PrepArgs &a, uint64_t xbytes_n, hipStream_t s) {
-    if (xbytes_n) {
-        uint64_t blocks = (xbytes_n / 4 + 255) / 256;
-        if (blocks > 4096) blocks = 4096;
-        hipLaunchKernelGGL(k_remap_x, dim3((uint32_t)blocks), dim3(256), 0, s, a.lut, a.xbytes,
-                           a.xcodes, xbytes_n);
-    }
-    hipLaunchKernelGGL(k_zero, dim3(512), dim3(256), 0, s, a);
-    if (a.nseg) {
-        uint32_t blocks = a.nseg < 65536 ? a.nseg : 65536;
-        hipLaunchKernelGGL(k_streams, dim3(blocks, 8), dim3(256), 0, s, a);
-    }
-    return hipGetLastError();
-}
-
-// --------------------------------------------------------------------------
-// fill
-// --------------------------------------------------------------------------
-
-size_t fill_lds_bytes(int wpl, int sigma) {
-    return (size_t)(kFillBlock / 64) * (size_t)(sigma + 1) * (size_t)wpl * 64 * sizeof(uint64_t);
-}
-
-// One column step for WPL words of one lane: U = V & M, S = V + U + carry
-// (64*WPL-bit add, carry in and out as a wave lane mask in an SGPR pair),
-// V' = S | (V & ~M).  Six VALU instructions per 64 cells.
-//
-// The carry mask is written by a VALU instruction (v_addc_co_u32) and read
-// by the next v_addc_co_u32; gfx950 needs two wait states between the two,
-// which the order below provides with independent instructions: inside a
-// word the low-half bitop3 and the high-half AND sit between the two adds;
-// across words the high-half bitop3 of the previous word and the low-half
-// AND of the next one do.  The carry mask coming in is always written by
-// scalar instructions and the one going out is only read by scalar
-// instructions, which need no wait states.
-template <int WPL>
-__device__ __forceinline__ void column_step(uint32_t (&vlo)[WPL], uint32_t (&vhi)[WPL],
-                                            const uint64_t (&M)[WPL], uint64_t &carry) {
-#pragma unroll
-    for (int q = 0; q < WPL; ++q) {
-        const uint32_t mlo = (uint32_t)M[q], mhi = (uint32_t)(M[q] >> 32);
-        uint32_t t0, t1;
-        asm("v_and_b32 %[ulo], %[vlo], %[mlo]\n\t"
-            "v_addc_co_u32 %[ulo], %[c], %[vlo], %[ulo], %[c]\n\t"
-            "v_bitop3_b32 %[vlo], %[ulo], %[vlo], %[mlo] bitop3:0xf4\n\t"
-            "v_and_b32 %[uhi], %[vhi], %[mhi]\n\t"
-            "v_addc_co_u32 %[uhi], %[c], %[vhi], %[uhi], %[c]\n\t"
-            "v_bitop3_b32 %[vhi], %[uhi], %[vhi], %[mhi] bitop3:0xf4"
-            : [vlo] "+v"(vlo[q]), [vhi] "+v"(vhi[q]), [c] "+s"(carry), [ulo] "=&v"(t0),
-              [uhi] "=&v"(t1)
-            : [mlo] "v"(mlo), [mhi] "v"(mhi));
-    }
-}
-
-// Make a value the compiler cannot prove wave-uniform live in SGPRs again (a
-// no-op when it already does).
-__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// Sixteen stream values (two per dword) starting at step t0.
-__device__ __forceinline__ void load16(const uint16_t *ys, uint32_t t0, uint32_t (&d)[8]) {
-    const uint16_t *p = ys + t0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) d[e] = (uint32_t)p[2 * e] | ((uint32_t)p[2 * e + 1] << 16);
-}
-
-#ifndef LCS_FILL_HOIST
-#define LCS_FILL_HOIST 8
-#endif
-
-// Sixteen column steps t..t+15 of one lane.  The carry-in lane mask of a
-// step is the carry-out mask of the previous step shifted up by one lane,
-// with segment starts cleared; with CHAIN, lane 0 takes the hand-over bit of
-// the feeding item (inbits, one bit per step) and lane 63's carry-out is
-// collected into outbits for the next item.  With TB, every lane's carry-in
-// bits are accumulated (newest in bit 0) and stored every 32 steps.
-template <int WPL, bool TB, bool CHAIN>
-__device__ __forceinline__ void run16(const uint32_t (&Yg)[8], uint32_t t, const char *lanecol,
-                                      uint64_t notstart, uint64_t &cmask, uint32_t &acc,
-                                      uint32_t *cbp, uint32_t (&vlo)[WPL], uint32_t (&vhi)[WPL],
-                                      uint64_t &inbits, uint64_t &outbits) {
-    constexpr int H = LCS_FILL_HOIST;   // steps whose match masks are read together
-#pragma unroll
-    for (int h = 0; h < 16 / H; ++h) {
-        // the match masks of H steps are read up front: they depend on the
-        // stream only, so their LDS latency overlaps the column steps
-        uint64_t Mg[H][WPL];
-#pragma unroll
-        for (int e = 0; e < H; ++e) {
-            const int s = h * H + e;
-            const uint32_t y2 = Yg[s >> 1];
-            const uint32_t off = (s & 1) ? (y2 >> 16) : (y2 & 0xffffu);
-            const char *row = lanecol + off;
-#pragma unroll
-            for (int q = 0; q < WPL; ++q) Mg[e][q] = *(const uint64_t *)(row + q * 512);
-        }
-#pragma unroll
-        for (int e = 0; e < H; ++e) {
-            uint64_t cm = cmask;
-            if (CHAIN) {
-                cm |= inbits & 1ull;
-                inbits >>= 1;
-            }
-            if (TB) {
-                uint32_t cj;
-                acc = __builtin_addc(acc, acc, (uint32_t)__builtin_amdgcn_inverse_ballot_w64(cm), &cj);
-                if (h * H + e == 15 && (t & 16u)) cbp[(size_t)((t + 15) >> 5) * 64] = acc;
-            }
-            column_step<WPL>(vlo, vhi, Mg[e], cm);
-            if (CHAIN) {
-                outbits = (outbits >> 1) | (cm & 0x8000000000000000ull);
-                // pin the accumulation to this step: sunk to its single use,
-                // it would keep every step's carry mask alive until the chunk end
-                asm volatile("" : "+s"(outbits), "+s"(inbits));
-            }
-            cmask = (cm << 1) & notstart;
-        }
-        // keep the scheduler from spreading the scalar work of many steps
-        // across each other (it would hold dozens of masks live)
-        __builtin_amdgcn_sched_barrier(0);
-    }
-}
-
-// Y stream element: code * (WPL * 512), i.e. the byte offset of the code's
-// row of match masks in the wave's LDS block ([symbol][word][lane] layout).
-template <int WPL, bool TB>
-__global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
-    extern __shared__ uint64_t smem[];
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int sig1 = a.sigma + 1;
-    constexpr uint32_t RS = WPL * 64;            // words per symbol row
-    uint64_t *pm = smem + (size_t)wv * sig1 * RS;
-    // this lane's column of the wave's block; a stream value is a byte offset
-    const char *lanecol = (const char *)(pm + lane);
-
-    for (;;) {
-        uint32_t ticket = 0;
-        if (lane == 0) ticket = atomicAdd(a.queue, 1u);
-        ticket = __builtin_amdgcn_readfirstlane(ticket);
-        if (ticket >= a.item_end - a.item_begin) return;
-        const uint32_t item = a.item_begin + ticket;
-
-        const size_t li = (size_t)item * 64 + lane;
-        const int32_t pair = a.ln_pair[li];
-        const uint32_t word0 = a.ln_word0[li];
-        const uint32_t skew = a.ln_skew[li];
-        const uint64_t ysoff = a.ln_ys[li];
-        const uint32_t T = a.it_T[item];
-        const int32_t prev = a.it_prev[item];
-        const bool feeds = a.it_feeds[item] != 0;
-
-        // ---- match masks of this lane's rows (LDS, own column only) ----
-        for (int c = 0; c < sig1; ++c)
-#pragma unroll
-            for (int q = 0; q < WPL; ++q) pm[c * RS + q * 64 + lane] = 0;
-        uint32_t m = 0;
-        if (pair >= 0) {
-            m = a.pair_m[pair];
-            const uint8_t *xc = a.xcodes + a.pair_xoff[pair];
-            for (int q = 0; q < WPL; ++q) {
-                const uint32_t row0 = (word0 + q) * 64u;
-                if (row0 >= m) break;
-                uint64_t *col = pm + q * 64 + lane;
-                const uint32_t cnt = (m - row0) < 64u ? (m - row0) : 64u;
-#pragma unroll 1
-                for (uint32_t r0 = 0; r0 < cnt; r0 += 4) {
-                    // the X arena is padded to 64 bytes per sequence
-                    const uint32_t w4 = *(const uint32_t *)(xc + row0 + r0);
-#pragma unroll
-                    for (int by = 0; by < 4; ++by) {
-                        const uint32_t r = r0 + by;
-                        if (r < cnt) {
-                            const uint32_t c = (w4 >> (8 * by)) & 0xffu;
-                            atomicOr((unsigned long long *)(col + c * RS), 1ull << r);
-                        }
-                    }
-                }
-            }
-        }
-
-        // ---- column steps ----
-        uint32_t vlo[WPL], vhi[WPL];
-#pragma unroll
-        for (int q = 0; q < WPL; ++q) { vlo[q] = ~0u; vhi[q] = ~0u; }
-        const uint16_t *ys = a.ystream + ysoff - skew;
-        const uint64_t startmask = __builtin_amdgcn_ballot_w64(pair < 0 || word0 == 0);
-        const uint64_t notstart = ~startmask;
-        uint64_t cmask = 0;
-        uint32_t acc = 0;
-        const uint32_t nch = T / 64;
-        uint64_t *ckp = nullptr;
-        uint32_t *cbp = nullptr;
-        if (TB) {
-            ckp = a.ckpt + a.it_ck[item] + lane;
-            cbp = a.cbits + a.it_cb[item] + lane;
-        }
-        // Carry hand-over between chained items: chunk c of a feeder is two
-        // 64-bit words, each a 32-bit tag (c + 1) above 32 carry bits, written
-        // with relaxed agent-scope atomic stores; the consumer accepts a word
-        // once its tag matches.  The words carry their own validity, so no
-        // release/acquire fence (an L2 write-back on this chip) is needed;
-        // the buffer is zeroed before every pass.
-        uint64_t *xf_out = feeds ? a.xfer + a.it_xf[item] : nullptr;
-        uint64_t *xf_in = prev >= 0 ? a.xfer + a.it_xf[prev] : nullptr;
-        bool aborted = false;
-        // Stream values, two per dword, in a ring of four 16-step groups; the
-        // group 32 steps ahead is requested before the current one is used,
-        // so the stream's memory latency hides behind two groups of work.
-        uint32_t Y0[8], Y1[8], Y2[8], Y3[8];
-        load16(ys, 0, Y0);
-        load16(ys, 16, Y1);
-        const bool chain = prev >= 0 || feeds;
-        // The longest items bound the kernel's duration: let the SIMD issue
-        // their instructions first; shorter items fill the remaining slots.
-        if (T >= a.prio_T) __builtin_amdgcn_s_setprio(2);
-        else __builtin_amdgcn_s_setprio(0);
-        uint64_t pw0 = 0, pw1 = 0;   // hand-over words requested one group early
-
-        for (uint32_t c = 0; c < nch; ++c) {
-            uint64_t inbits = 0, outbits = 0;
-            if (prev >= 0 && c > 0) {
-                uint64_t w0 = uniform64(pw0), w1 = uniform64(pw1);
-                uint32_t spins = 0;
-                while ((uint32_t)(w0 >> 32) != c || (uint32_t)(w1 >> 32) != c) {
-                    // bounded wait for the feeding item to finish chunk c-1
-                    if (++spins > a.spin_limit) { aborted = true; break; }
-                    __builtin_amdgcn_s_sleep(1);
-                    w0 = uniform64(__hip_atomic_load(xf_in + 2 * (c - 1), __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT));
-                    w1 = uniform64(__hip_atomic_load(xf_in + 2 * (c - 1) + 1, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT));
-                }
-                if (aborted) break;
-                inbits = (w1 << 32) | (w0 & 0xffffffffull);
-            }
-            if (TB && ((c * 64u) % (uint32_t)a.ckpt_every) == 0) {
-                uint64_t *dst = ckp + (size_t)((c * 64u) / (uint32_t)a.ckpt_every) * RS;
-#pragma unroll
-                for (int q = 0; q < WPL; ++q) dst[q * 64] = ((uint64_t)vhi[q] << 32) | vlo[q];
-            }
-            const uint32_t t = c * 64u;
-            if (chain) {
-                load16(ys, t + 32, Y2);
-                run16<WPL, TB, true>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
-                load16(ys, t + 48, Y3);
-                run16<WPL, TB, true>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
-                load16(ys, t + 64, Y0);
-                run16<WPL, TB, true>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
-                load16(ys, t + 80, Y1);
-                if (prev >= 0) {
-                    pw0 = __hip_atomic_load(xf_in + 2 * c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    pw1 = __hip_atomic_load(xf_in + 2 * c + 1, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-                }
-                run16<WPL, TB, true>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
-                if (feeds && lane == 0) {
-                    const uint64_t tag = (uint64_t)(c + 1) << 32;
-                    __hip_atomic_store(xf_out + 2 * c, tag | (outbits & 0xffffffffull),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(xf_out + 2 * c + 1, tag | (outbits >> 32), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                }
-            } else {
-                load16(ys, t + 32, Y2);
-                run16<WPL, TB, false>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
-                load16(ys, t + 48, Y3);
-                run16<WPL, TB, false>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
-                load16(ys, t + 64, Y0);
-                run16<WPL, TB, false>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
-                load16(ys, t + 80, Y1);
-                run16<WPL, TB, false>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
-            }
-        }
-        if (aborted) {
-            if (lane == 0) atomicOr(a.error, 1u);
-            return;
-        }
-
-        // ---- length: zero bits among the valid rows ----
-        if (pair >= 0) {
-            uint32_t zeros = 0;
-#pragma unroll
-            for (int q = 0; q < WPL; ++q) {
-                const uint32_t row0 = (word0 + q) * 64u;
-                if (row0 < m) {
-                    const uint32_t cnt = (m - row0) < 64u ? (m - row0) : 64u;
-                    const uint64_t mask = cnt == 64u ? ~0ull : ((1ull << cnt) - 1);
-                    const uint64_t v = ((uint64_t)vhi[q] << 32) | vlo[q];
-                    zeros += cnt - (uint32_t)__builtin_popcountll(v & mask);
-                }
-            }
-            if (zeros) atomicAdd((unsigned long long *)(a.out_len + pair), (unsigned long long)zeros);
-        }
-    }
-}
-
-const void *fill_symbol(int wpl, bool tb) {
-    switch (wpl) {
-        case 1: return tb ? (const void *)&k_fill<1, true> : (const void *)&k_fill<1, false>;
-        case 2: return tb ? (const void *)&k_fill<2, true> : (const void *)&k_fill<2, false>;
-        case 4: return tb ? (const void *)&k_fill<4, true> : (const void *)&k_fill<4, false>;
-        default: return tb ? (const void *)&k_fill<8, true> : (const void *)&k_fill<8, false>;
-    }
-}
-
-hipError_t launch_fill(int wpl, bool tb, const FillArgs &a, uint32_t grid, hipStream_t s) {
-    const size_t lds = fill_lds_bytes(wpl, a.sigma);
-#define LCS_FILL_CASE(W)                                                                  \
-    case W:                                                                               \
-        if (tb)                                                                           \
-            hipLaunchKernelGGL((k_fill<W, true>), dim3(grid), dim3(kFillBlock), lds, s, a); \
-        else                                                                              \
-            hipLaunchKernelGGL((k_fill<W, false>), dim3(grid), dim3(kFillBlock), lds, s, a); \
-        break;
-    switch (wpl) {
-        LCS_FILL_CASE(1)
-        LCS_FILL_CASE(2)
-        LCS_FILL_CASE(4)
-        LCS_FILL_CASE(8)
-        default: return hipErrorInvalidValue;
-    }
-#undef LCS_FILL_CASE
-    return hipGetLastError();
-}
 
 // --------------------------------------------------------------------------
 // traceback
@@ -461,18 +35,6 @@ __host__ __device__ static inline size_t tb_wave_words(int wpl, int sigma, int K
 
 size_t tb_lds_bytes(int wpl, int sigma, int K, int nb, int bands) {
     return (size_t)(kTbBlock / 64) * tb_wave_words(wpl, sigma, K, nb, bands) * sizeof(uint64_t);
-}
-
-// Lane `idx` (wave-uniform) of a 64-bit per-lane value, as a scalar.
-__device__ __forceinline__ uint64_t readlane64(uint64_t v, int32_t idx) {
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, idx);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), idx);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
 }
 
 // V of one band over the 2^LOGK steps of one tile, from the checkpoint V0
