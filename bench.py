@@ -61,9 +61,10 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, wpl: int, ckpt: int):
     """HBM bytes per fill launch from the committed rocprofv3 counter runs,
-    or None when they were taken on a different kernel source or workload."""
+    or None when they were taken on a different kernel source, workload or
+    plan (words per lane, checkpoint interval)."""
     import hashlib
     src = os.path.join(ROOT, "paper_1306_4627_amd", "csrc", "fill.hip")
     rec_file = os.path.join(ROOT, "profiles", "k_fill_batch_related_4096.md")
@@ -72,7 +73,8 @@ def measured_traffic(workload: str):
         for line in open(rec_file):
             if line.startswith("traffic-record:"):
                 rec = json.loads(line.split(":", 1)[1])
-                if rec["source_sha256_prefix"] == h and rec["workload"] == workload:
+                if (rec["source_sha256_prefix"] == h and rec["workload"] == workload
+                        and rec.get("words_per_lane") == wpl and rec.get("ckpt_interval") == ckpt):
                     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         pass
@@ -123,6 +125,8 @@ def main() -> int:
     ap.add_argument("--cpu-cells", type=float, default=6e9)
     ap.add_argument("--wpl", type=int, default=0)
     ap.add_argument("--ckpt", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default tuning instead of a timed search")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES bytes (the "
                          "reference for scaling HBM byte counters) and exit")
@@ -148,8 +152,14 @@ def main() -> int:
     cells = float(sum(p.cells for p in ps))
     ctx = lcs.Context(0)
     log(f"workload {args.workload}: {len(pairs)} pairs, {cells:.3e} cells")
-    batch = lcs.Batch(ctx, pairs, alpha, traceback=tb, graph=True,
-                      words_per_lane=args.wpl, ckpt_interval=args.ckpt)
+    tuning = {"words_per_lane": args.wpl, "ckpt_interval": args.ckpt}
+    tune_s = None
+    if not args.no_autotune and not args.wpl and not args.ckpt:
+        t0 = time.perf_counter()
+        tuning, tune_ms = lcs.autotune(ctx, pairs, alpha, traceback=tb, graph=True)
+        tune_s = time.perf_counter() - t0
+        log(f"autotune: {tuning} ({tune_ms:.3f} ms per pass, search {tune_s:.1f} s)")
+    batch = lcs.Batch(ctx, pairs, alpha, traceback=tb, graph=True, **tuning)
     info = batch.info()
     log(f"plan: {info}")
     for _ in range(args.warmup):
@@ -184,11 +194,13 @@ def main() -> int:
         "config": config,
         "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_TCUPS, 1),
                      "unit": "TCUPS", "frac": round(achieved / PEAK_TCUPS, 4),
-                     "traffic": measured_traffic(config["workload"]),
+                     "traffic": measured_traffic(config["workload"], info["words_per_lane"],
+                                                 info["ckpt_interval"]),
                      "kernel": "k_fill", "fill_ms": round(fill_avg, 4),
                      "eager_pass_ms": round(float(np.mean(eager_ms)), 4)},
         "plan": {k: info[k] for k in ("groups", "lanes", "lane_steps", "words_per_lane",
                                       "ckpt_interval", "classes", "device_bytes")},
+        "tuning": {"chosen": tuning, "search_s": None if tune_s is None else round(tune_s, 2)},
     }
     if not args.no_plain and len(pairs) > 1:
         log("plain per-pair leg")

@@ -215,6 +215,23 @@ lcs_status lcs_batch_time(lcs_batch *batch, int eager, float *total_ms, float *f
 /* Release a batch (NULL is ignored). */
 void lcs_batch_destroy(lcs_batch *batch);
 
+/* Timed search for the tuning of a batch (the batched form's autotuner).
+ * Plans and runs the batch (flags as for lcs_batch_create) under candidate
+ * tunings -- words_per_lane 1, 2, 4, 8 as the alphabet allows, then with
+ * LCS_WANT_TRACEBACK the checkpoint interval 64 or 128 and the tiles per
+ * traceback round -- and writes the fastest to *best and its pass time (ms,
+ * graph replay when LCS_USE_GRAPH is set) to *best_ms (may be NULL).  Each
+ * candidate uploads the inputs and runs three passes; results are not kept.
+ * The answer is cached in the context under the batch's shape (flags,
+ * alphabet size, and log2 of the pair count, of the longest X and Y and, in
+ * quarters, of the total cells); a later call with a batch of the same shape
+ * returns it without running anything.  Candidates that do not fit the
+ * memory budget are skipped; LCS_ERR_NOMEM if none fits.  Argument and
+ * symbol errors as for lcs_batch_create. */
+lcs_status lcs_autotune(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                        const lcs_alphabet *alphabet, uint32_t flags, lcs_tuning *best,
+                        float *best_ms);
+
 /* Host-only planning check (no device needed).  Packs `count` pairs of the
  * given lengths for `words_per_lane` and reports the same figures
  * lcs_batch_info would (device_bytes excluded).  Used to test the packer. */

@@ -4,12 +4,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "kernels.hpp"
@@ -20,6 +23,17 @@ using namespace lcs;
 
 #define LCS_VERSION_STRING "lcs-mi355x 0.1 (gfx950)"
 
+// Shape of a batch as the autotuner's cache sees it: flags, alphabet size,
+// and base-2 logarithms of the pair count, the longest X and Y, and (in
+// quarters) the total cell count.
+struct TuneKey {
+    uint32_t flags, sigma, lcount, lm, ln, lcells4;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(flags, sigma, lcount, lm, ln, lcells4) <
+               std::tie(o.flags, o.sigma, o.lcount, o.lm, o.ln, o.lcells4);
+    }
+};
+
 struct lcs_ctx {
     int device = 0;
     hipStream_t own_stream = nullptr;
@@ -28,6 +42,7 @@ struct lcs_ctx {
     size_t in_use = 0;
     int num_cus = 0;
     std::string arch;
+    std::map<TuneKey, std::pair<lcs_tuning, float>> tune_cache;   // autotuner results
 };
 
 namespace {
@@ -1065,6 +1080,106 @@ extern "C" lcs_status lcs_traceback_batch(lcs_ctx *ctx, const lcs_pair *pairs, u
 // --------------------------------------------------------------------------
 // host-only planning checks
 // --------------------------------------------------------------------------
+
+// --------------------------------------------------------------------------
+// autotuner
+// --------------------------------------------------------------------------
+
+static uint32_t ilog2_u64(uint64_t v) { return v ? 63u - (uint32_t)__builtin_clzll(v) : 0u; }
+
+extern "C" lcs_status lcs_autotune(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                                   const lcs_alphabet *alphabet, uint32_t flags,
+                                   lcs_tuning *best, float *best_ms) {
+    if (!ctx || !best) return LCS_ERR_ARG;
+    if (flags & ~(uint32_t)(LCS_WANT_TRACEBACK | LCS_USE_GRAPH)) return LCS_ERR_ARG;
+    lcs_status st = check_pairs(pairs, count);
+    if (st) return st;
+    uint8_t lut[256];
+    bool valid[256];
+    int sigma = 0;
+    st = make_lut(alphabet, lut, valid, &sigma);
+    if (st) return st;
+    if (sigma > 127 || max_wpl(sigma) == 0) return LCS_ERR_UNSUPPORTED;
+    uint64_t mm = 0, mn = 0;
+    double cells = 0;
+    for (uint64_t k = 0; k < count; ++k) {
+        mm = std::max<uint64_t>(mm, pairs[k].m);
+        mn = std::max<uint64_t>(mn, pairs[k].n);
+        cells += (double)pairs[k].m * (double)pairs[k].n;
+    }
+    const TuneKey key{flags, (uint32_t)sigma, ilog2_u64(count), ilog2_u64(mm), ilog2_u64(mn),
+                      cells >= 1 ? (uint32_t)(4.0 * std::log2(cells)) : 0u};
+    auto hit = ctx->tune_cache.find(key);
+    if (hit != ctx->tune_cache.end()) {
+        *best = hit->second.first;
+        if (best_ms) *best_ms = hit->second.second;
+        return LCS_OK;
+    }
+    // one candidate: plan, one untimed pass, then the best of two timed passes
+    auto measure = [&](const lcs_tuning &t, float *ms) -> lcs_status {
+        lcs_batch *b = nullptr;
+        lcs_status s2 = build_batch(ctx, pairs, count, alphabet, flags, &t, &b);
+        if (s2) return s2;
+        float tot = 0.f, f = 0.f, bestt = 1e30f;
+        s2 = lcs_batch_time(b, 0, &tot, &f);
+        for (int r = 0; r < 2 && !s2; ++r) {
+            s2 = lcs_batch_time(b, 0, &tot, &f);
+            bestt = std::min(bestt, tot);
+        }
+        free_batch(b);
+        if (!s2) *ms = bestt;
+        return s2;
+    };
+    lcs_tuning cur{};
+    float cur_ms = 1e30f;
+    bool any = false;
+    auto consider = [&](const lcs_tuning &t) -> lcs_status {
+        float ms = 0.f;
+        lcs_status s2 = measure(t, &ms);
+        if (s2 == LCS_ERR_NOMEM || s2 == LCS_ERR_TOO_LONG || s2 == LCS_ERR_UNSUPPORTED) return LCS_OK;
+        if (s2) return s2;
+        if (!any || ms < cur_ms) {
+            cur = t;
+            cur_ms = ms;
+            any = true;
+        }
+        return LCS_OK;
+    };
+    // words per lane first, then (with tracebacks) the checkpoint interval
+    // and the tiles per recompute round
+    for (int w : {1, 2, 4, 8}) {
+        if (!wpl_fits(sigma, w)) continue;
+        lcs_tuning t{};
+        t.words_per_lane = w;
+        st = consider(t);
+        if (st) return st;
+    }
+    if (!any) return LCS_ERR_NOMEM;
+    if (flags & LCS_WANT_TRACEBACK) {
+        const lcs_tuning base = cur;
+        for (int k : {64, 128}) {
+            lcs_tuning t = base;
+            t.ckpt_interval = k;
+            st = consider(t);
+            if (st) return st;
+        }
+        const lcs_tuning base2 = cur;
+        const int K = base2.ckpt_interval ? base2.ckpt_interval : 64;
+        const int span = std::max(1, 256 / K);
+        for (int nb : {span - 1, span + 1}) {
+            if (nb < 1 || nb > 8) continue;
+            lcs_tuning t = base2;
+            t.tb_tiles = nb;
+            t.tb_bands = 2;
+            st = consider(t);
+            if (st) return st;
+        }
+    }
+    ctx->tune_cache[key] = {cur, cur_ms};
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    return LCS_OK;
+}
 
 static lcs_status plan_only(const uint64_t *m, const uint64_t *n, uint64_t count,
                             uint16_t alphabet_size, uint32_t flags, const lcs_tuning *tuning,

@@ -124,6 +124,9 @@ def _load() -> ctypes.CDLL:
     lib.lcs_batch_time.restype = i32
     lib.lcs_batch_destroy.argtypes = [vp]
     lib.lcs_batch_destroy.restype = None
+    lib.lcs_autotune.argtypes = [vp, P(lcs_pair), u64, P(lcs_alphabet), ctypes.c_uint32,
+                                 P(lcs_tuning), P(ctypes.c_float)]
+    lib.lcs_autotune.restype = i32
     lib.lcs_plan_describe.argtypes = [u64p, u64p, u64, ctypes.c_uint16, ctypes.c_uint32,
                                       P(lcs_tuning), P(lcs_batch_stats)]
     lib.lcs_plan_describe.restype = i32
@@ -366,6 +369,21 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def autotune(ctx: Context, pairs, alphabet="dna", traceback: bool = False,
+             graph: bool = False) -> Tuple[dict, float]:
+    """Timed search for a batch's tuning (``lcs_autotune``); returns the
+    tuning fields as a dict (usable as ``Batch(**tuning)``) and its pass time
+    in ms."""
+    pp = _Pairs(pairs)
+    al = _alpha(alphabet)
+    flags = (LCS_WANT_TRACEBACK if traceback else 0) | (LCS_USE_GRAPH if graph else 0)
+    t = lcs_tuning()
+    ms = ctypes.c_float(0.0)
+    _check(_lib.lcs_autotune(ctx.h, pp.ptr(), pp.count, ctypes.byref(al.c), flags, ctypes.byref(t),
+                             ctypes.byref(ms)), "lcs_autotune")
+    return {k: int(getattr(t, k)) for k, _ in lcs_tuning._fields_ if k != "plain"}, float(ms.value)
 
 
 def plan_describe(m, n, alphabet_size: int = 4, traceback: bool = False, **tuning) -> dict:

@@ -47,6 +47,13 @@ def test_create_without_device_fails_cleanly():
     assert e.value.status == lcs.LCS_ERR_DEVICE
 
 
+def test_autotune_arguments_rejected_before_any_device_call():
+    L = lcs.lib()
+    best = lcs.lcs_tuning()
+    al = lcs.lcs_alphabet(4, ctypes.cast(ctypes.c_char_p(b"ACGT"), ctypes.POINTER(ctypes.c_uint8)))
+    assert L.lcs_autotune(None, None, 0, ctypes.byref(al), 0, ctypes.byref(best), None) == lcs.LCS_ERR_ARG
+
+
 def test_null_arguments_rejected_before_any_device_call():
     L = lcs.lib()
     out = ctypes.c_uint64(7)

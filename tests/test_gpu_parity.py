@@ -163,6 +163,33 @@ def test_traceback_strips_plain_and_tiles(ctx, lcs, tiles):
             assert b.tracebacks() == want, rep
 
 
+def test_autotune_picks_a_valid_tuning_and_caches_it(ctx, lcs):
+    g = inputs.rng(6490)
+    pairs = []
+    for _ in range(60):
+        m = int(np.exp(g.uniform(np.log(64), np.log(6000))))
+        x = _rand(g, m, inputs.DNA)
+        y, _ = inputs.mutate(g, x, float(g.uniform(0.05, 0.3)), inputs.DNA)
+        pairs.append((x, y))
+    _say("autotune")
+    tun, ms = lcs.autotune(ctx, pairs, "dna", traceback=True, graph=True)
+    assert tun["words_per_lane"] in (1, 2, 4, 8) and ms > 0
+    assert tun["ckpt_interval"] in (0, 64, 128, 256)
+    import time
+    t0 = time.perf_counter()
+    tun2, ms2 = lcs.autotune(ctx, pairs, "dna", traceback=True, graph=True)
+    assert tun2 == tun and ms2 == ms and time.perf_counter() - t0 < 0.5   # from the cache
+    with lcs.Batch(ctx, pairs, "dna", traceback=True, graph=True, **tun) as b:
+        b.run()
+        assert np.array_equal(b.lengths(), _oracle_lengths(pairs))
+        assert b.tracebacks() == _oracle_tracebacks(pairs)
+    # lengths only: a different shape key, a words-per-lane search of its own
+    tun3, _ = lcs.autotune(ctx, pairs, "dna")
+    with lcs.Batch(ctx, pairs, "dna", **tun3) as b:
+        b.run()
+        assert np.array_equal(b.lengths(), _oracle_lengths(pairs))
+
+
 @pytest.mark.parametrize("wpl", [1, 2, 4])
 def test_chained_items_long_rows(ctx, lcs, wpl):
     # rows beyond one wave (64 lanes * wpl words * 64 bits) chain several
