@@ -114,6 +114,42 @@ def cpu_baseline(pairs, traceback: bool, budget_cells: float, threads: int):
                       f"{'length+traceback' if traceback else 'length'}, {dt:.1f} s"}
 
 
+def serve_leg(lcs, ctx, rates, count: int):
+    """The request server under Poisson arrivals at each offered rate: every
+    request submitted at its arrival time, then collected; latency is the
+    library's submit-to-completion time of each request."""
+    from paper_1306_4627_amd import inputs
+    out = []
+    for k, rate in enumerate(rates):
+        reqs = inputs.serve_stream(rate, count, seed_offset=51 + k)
+        cells = float(sum(int(r.x.size) * int(r.y.size) for r in reqs))
+        with lcs.Server(ctx, mem_budget_bytes=8 << 30) as srv:
+            tickets = []
+            t0 = time.perf_counter()
+            for r in reqs:
+                while time.perf_counter() - t0 < r.arrival_s:
+                    pass
+                tickets.append(srv.submit(r.x, r.y, r.alphabet, traceback=r.want_traceback))
+            lat = []
+            for t in tickets:
+                srv.wait(t)
+                lat.append(srv.result(t)[2])
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+        lat_ms = np.array(lat) / 1e6
+        out.append({"offered_rps": rate, "requests": count,
+                    "achieved_rps": round(count / wall, 1),
+                    "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                    "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+                    "GCUPS": round(cells / wall / 1e9, 2),
+                    "batches": st["batches"], "max_inflight": st["max_inflight"],
+                    "plan_ms_per_batch": round(st["plan_ns"] / max(st["batches"], 1) / 1e6, 3),
+                    "device_ms_per_batch": round(st["device_ns"] / max(st["batches"], 1) / 1e6, 3),
+                    "collect_ms_per_batch": round(st["collect_ns"] / max(st["batches"], 1) / 1e6, 3)})
+        log(f"serve rate {rate}/s: {out[-1]}")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +158,10 @@ def main() -> int:
     ap.add_argument("--workload", default="batch_related")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-pair leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the request-server leg")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only run the request-server leg and print its results")
     ap.add_argument("--cpu-cells", type=float, default=6e9)
     ap.add_argument("--wpl", type=int, default=0)
     ap.add_argument("--ckpt", type=int, default=0)
@@ -147,6 +187,12 @@ def main() -> int:
 
     from paper_1306_4627_amd import lcs
 
+    if args.serve_only:
+        ctx = lcs.Context(0)
+        print(json.dumps({"serving": serve_leg(lcs, ctx, (1000, 8000, 64000), args.serve_requests)}),
+              flush=True)
+        ctx.close()
+        return 0
     ps, alpha, tb, config = make_workload(args.workload)
     pairs = [(p.x, p.y) for p in ps]
     cells = float(sum(p.cells for p in ps))
@@ -214,6 +260,11 @@ def main() -> int:
         out["plain_per_pair"] = {"value": round(cells / (t_plain * 1e-3) / 1e9, 2), "unit": "GCUPS",
                                  "ms": round(t_plain, 3)}
         out["batched_over_plain"] = round(value / out["plain_per_pair"]["value"], 2)
+    if not args.no_serve:
+        log("request-server leg")
+        out["serving"] = {"workload": "Poisson arrivals; |X|, |Y| log-uniform [100, 100000]; "
+                                      "alphabet DNA/protein/byte; traceback for half",
+                          "rates": serve_leg(lcs, ctx, (1000, 8000, 64000), args.serve_requests)}
     if not args.no_cpu:
         threads = min(len(os.sched_getaffinity(0)), 16)
         log(f"cpu oracle leg ({threads} threads)")

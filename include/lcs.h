@@ -42,6 +42,7 @@ extern "C" {
 #endif
 
 typedef enum {
+    LCS_PENDING = 1,          /* (request server) the request is queued or running */
     LCS_OK = 0,
     LCS_ERR_ARG = -1,         /* NULL pointer with non-zero length, bad flag or size */
     LCS_ERR_SYMBOL = -2,      /* a byte of X or Y is not in the alphabet */
@@ -231,6 +232,79 @@ void lcs_batch_destroy(lcs_batch *batch);
 lcs_status lcs_autotune(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
                         const lcs_alphabet *alphabet, uint32_t flags, lcs_tuning *best,
                         float *best_ms);
+
+/* ---- request server (continuous batching) --------------------------------
+ *
+ * A server accepts single LCS requests at any time and answers each one
+ * exactly as lcs_length / lcs_traceback would.  A dispatcher thread of its
+ * own gathers the requests waiting in arrival order -- the oldest one and
+ * the later ones with the same alphabet and traceback choice -- into a batch
+ * whenever one of its streams is free, and launches it while earlier
+ * batches still run, so requests that arrive during other work are admitted
+ * as streams and memory free up and their work overlaps on the device.
+ * Device memory for the resident requests (sequences, match masks,
+ * checkpoints, bitmaps) comes from one arena reserved from the context's
+ * budget at creation; a batch that does not fit the free arena is retried
+ * smaller or waits for running batches, and a request that cannot fit the
+ * empty arena fails with LCS_ERR_NOMEM.  Inputs are copied at submission;
+ * results stay with the server until lcs_result collects them.  While a
+ * server runs, its context may still be used for other calls from the
+ * caller's thread (other streams, other memory). */
+typedef struct lcs_server lcs_server;
+
+typedef struct {
+    size_t mem_budget_bytes;   /* arena size; 0 = half of what the context budget has left */
+    int32_t streams;           /* batches in flight at once, 1..16 (0 = 4) */
+    int32_t max_batch_pairs;   /* requests per batch (0 = 4096) */
+} lcs_server_config;
+
+typedef struct {
+    uint64_t submitted, completed, failed, cancelled;
+    uint64_t queued;           /* waiting for admission now */
+    uint64_t batches;          /* batches launched */
+    uint64_t max_inflight;     /* most batches running at once */
+    uint64_t cells;            /* sum of m*n over completed requests */
+    uint64_t arena_bytes, arena_peak_bytes;
+    uint64_t plan_ns;          /* dispatcher time planning, uploading and launching batches */
+    uint64_t collect_ns;       /* dispatcher time copying finished batches' results */
+    uint64_t device_ns;        /* sum over batches of launch-to-completion time */
+} lcs_server_stats;
+
+/* Start a server on the context (cfg may be NULL for the defaults). */
+lcs_status lcs_server_create(lcs_ctx *ctx, const lcs_server_config *cfg, lcs_server **out);
+
+/* Stop accepting requests, drop the queued ones, let running batches
+ * finish, release the arena and the streams (NULL is ignored). */
+void lcs_server_destroy(lcs_server *server);
+
+/* Queue one request (X, Y validated against the alphabet now; the bytes are
+ * copied).  want_traceback != 0 also recovers the canonical LCS string.
+ * *ticket names the request in the calls below. */
+lcs_status lcs_submit(lcs_server *server, const uint8_t *x, uint64_t m, const uint8_t *y,
+                      uint64_t n, const lcs_alphabet *alphabet, int want_traceback,
+                      uint64_t *ticket);
+
+/* LCS_PENDING while queued or running, LCS_OK when done, else the status the
+ * request failed with; LCS_ERR_ARG for an unknown ticket. */
+lcs_status lcs_poll(lcs_server *server, uint64_t ticket);
+
+/* As lcs_poll, after waiting up to timeout_us microseconds (< 0: no limit)
+ * for the request to finish. */
+lcs_status lcs_wait(lcs_server *server, uint64_t ticket, int64_t timeout_us);
+
+/* Collect a finished request: *len its LCS length, out (capacity out_cap)
+ * its LCS string when a traceback was requested, *latency_ns (may be NULL)
+ * the time from submission to completion.  Releases the ticket, also when
+ * the request failed (its status is returned).  LCS_PENDING if not finished;
+ * LCS_ERR_BUFFER (ticket kept) if out_cap is smaller than the string. */
+lcs_status lcs_result(lcs_server *server, uint64_t ticket, uint64_t *len, uint8_t *out,
+                      uint64_t out_cap, uint64_t *latency_ns);
+
+/* Withdraw a request that is still queued (LCS_ERR_ARG otherwise). */
+lcs_status lcs_cancel(lcs_server *server, uint64_t ticket);
+
+/* Counters since creation. */
+lcs_status lcs_server_stats_get(lcs_server *server, lcs_server_stats *out);
 
 /* Host-only planning check (no device needed).  Packs `count` pairs of the
  * given lengths for `words_per_lane` and reports the same figures

@@ -9,6 +9,7 @@
 // No cross-lane add is ever waited for inside a step.
 #include "kernels.hpp"
 #include "bitvec.hpp"
+#include "plan.hpp"
 
 namespace lcs {
 
@@ -17,7 +18,7 @@ namespace lcs {
 // --------------------------------------------------------------------------
 
 size_t fill_lds_bytes(int wpl, int sigma) {
-    return (size_t)(kFillBlock / 64) * (size_t)(sigma + 1) * (size_t)wpl * 64 * sizeof(uint64_t);
+    return (size_t)fill_waves(sigma, wpl) * (size_t)(sigma + 1) * (size_t)wpl * 64 * sizeof(uint64_t);
 }
 
 // Sixteen stream values (two per dword) starting at step t0.
@@ -37,7 +38,7 @@ __device__ __forceinline__ void load16(const uint16_t *ys, uint32_t t0, uint32_t
 // the feeding item (inbits, one bit per step) and lane 63's carry-out is
 // collected into outbits for the next item.  With TB, every lane's carry-in
 // bits are accumulated (newest in bit 0) and stored every 32 steps.
-template <int WPL, bool TB, bool CHAIN>
+template <int WPL, bool TB, bool CHAIN, bool RAW>
 __device__ __forceinline__ void run16(const uint32_t (&Yg)[8], uint32_t t, const char *lanecol,
                                       uint64_t notstart, uint64_t &cmask, uint32_t &acc,
                                       uint32_t *cbp, uint32_t (&vlo)[WPL], uint32_t (&vhi)[WPL],
@@ -52,7 +53,8 @@ __device__ __forceinline__ void run16(const uint32_t (&Yg)[8], uint32_t t, const
         for (int e = 0; e < H; ++e) {
             const int s = h * H + e;
             const uint32_t y2 = Yg[s >> 1];
-            const uint32_t off = (s & 1) ? (y2 >> 16) : (y2 & 0xffffu);
+            uint32_t off = (s & 1) ? (y2 >> 16) : (y2 & 0xffffu);
+            if (RAW) off <<= 9 + (WPL == 1 ? 0 : WPL == 2 ? 1 : WPL == 4 ? 2 : 3);
             const char *row = lanecol + off;
 #pragma unroll
             for (int q = 0; q < WPL; ++q) Mg[e][q] = *(const uint64_t *)(row + q * 512);
@@ -85,8 +87,9 @@ __device__ __forceinline__ void run16(const uint32_t (&Yg)[8], uint32_t t, const
 }
 
 // Y stream element: code * (WPL * 512), i.e. the byte offset of the code's
-// row of match masks in the wave's LDS block ([symbol][word][lane] layout).
-template <int WPL, bool TB>
+// row of match masks in the wave's LDS block ([symbol][word][lane] layout);
+// with RAW the plain code, shifted here.
+template <int WPL, bool TB, bool RAW>
 __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
     extern __shared__ uint64_t smem[];
     const int lane = threadIdx.x & 63;
@@ -205,18 +208,18 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
             const uint32_t t = c * 64u;
             if (chain) {
                 load16(ys, t + 32, Y2);
-                run16<WPL, TB, true>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                run16<WPL, TB, true, RAW>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
                 load16(ys, t + 48, Y3);
-                run16<WPL, TB, true>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                run16<WPL, TB, true, RAW>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
                 load16(ys, t + 64, Y0);
-                run16<WPL, TB, true>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                run16<WPL, TB, true, RAW>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
                 load16(ys, t + 80, Y1);
                 if (prev >= 0) {
                     pw0 = __hip_atomic_load(xf_in + 2 * c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     pw1 = __hip_atomic_load(xf_in + 2 * c + 1, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
                 }
-                run16<WPL, TB, true>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                run16<WPL, TB, true, RAW>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
                 if (feeds && lane == 0) {
                     const uint64_t tag = (uint64_t)(c + 1) << 32;
                     __hip_atomic_store(xf_out + 2 * c, tag | (outbits & 0xffffffffull),
@@ -226,13 +229,13 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
                 }
             } else {
                 load16(ys, t + 32, Y2);
-                run16<WPL, TB, false>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                run16<WPL, TB, false, RAW>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
                 load16(ys, t + 48, Y3);
-                run16<WPL, TB, false>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                run16<WPL, TB, false, RAW>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
                 load16(ys, t + 64, Y0);
-                run16<WPL, TB, false>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                run16<WPL, TB, false, RAW>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
                 load16(ys, t + 80, Y1);
-                run16<WPL, TB, false>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                run16<WPL, TB, false, RAW>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
             }
         }
         if (aborted) {
@@ -258,33 +261,42 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
     }
 }
 
-const void *fill_symbol(int wpl, bool tb) {
+const void *fill_symbol(int wpl, bool tb, bool raw) {
+    if (raw) {
+        if (wpl == 1) return tb ? (const void *)&k_fill<1, true, true> : (const void *)&k_fill<1, false, true>;
+        return tb ? (const void *)&k_fill<2, true, true> : (const void *)&k_fill<2, false, true>;
+    }
     switch (wpl) {
-        case 1: return tb ? (const void *)&k_fill<1, true> : (const void *)&k_fill<1, false>;
-        case 2: return tb ? (const void *)&k_fill<2, true> : (const void *)&k_fill<2, false>;
-        case 4: return tb ? (const void *)&k_fill<4, true> : (const void *)&k_fill<4, false>;
-        default: return tb ? (const void *)&k_fill<8, true> : (const void *)&k_fill<8, false>;
+        case 1: return tb ? (const void *)&k_fill<1, true, false> : (const void *)&k_fill<1, false, false>;
+        case 2: return tb ? (const void *)&k_fill<2, true, false> : (const void *)&k_fill<2, false, false>;
+        case 4: return tb ? (const void *)&k_fill<4, true, false> : (const void *)&k_fill<4, false, false>;
+        default: return tb ? (const void *)&k_fill<8, true, false> : (const void *)&k_fill<8, false, false>;
     }
 }
 
+int fill_block(int wpl, int sigma) { return 64 * fill_waves(sigma, wpl); }
+
 hipError_t launch_fill(int wpl, bool tb, const FillArgs &a, uint32_t grid, hipStream_t s) {
+    if (!wpl_fits(a.sigma, wpl)) return hipErrorInvalidValue;
     const size_t lds = fill_lds_bytes(wpl, a.sigma);
-#define LCS_FILL_CASE(W)                                                                  \
-    case W:                                                                               \
-        if (tb)                                                                           \
-            hipLaunchKernelGGL((k_fill<W, true>), dim3(grid), dim3(kFillBlock), lds, s, a); \
-        else                                                                              \
-            hipLaunchKernelGGL((k_fill<W, false>), dim3(grid), dim3(kFillBlock), lds, s, a); \
-        break;
-    switch (wpl) {
-        LCS_FILL_CASE(1)
-        LCS_FILL_CASE(2)
-        LCS_FILL_CASE(4)
-        LCS_FILL_CASE(8)
-        default: return hipErrorInvalidValue;
+    const dim3 block((uint32_t)fill_block(wpl, a.sigma));
+    const bool raw = raw_stream(a.sigma, wpl);
+#define LCS_FILL_CASE(W, R)                                                            \
+    if (wpl == W && raw == R) {                                                        \
+        if (tb)                                                                        \
+            hipLaunchKernelGGL((k_fill<W, true, R>), dim3(grid), block, lds, s, a);    \
+        else                                                                           \
+            hipLaunchKernelGGL((k_fill<W, false, R>), dim3(grid), block, lds, s, a);   \
+        return hipGetLastError();                                                      \
     }
+    LCS_FILL_CASE(1, false)
+    LCS_FILL_CASE(2, false)
+    LCS_FILL_CASE(4, false)
+    LCS_FILL_CASE(8, false)
+    LCS_FILL_CASE(1, true)
+    LCS_FILL_CASE(2, true)
 #undef LCS_FILL_CASE
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 }  // namespace lcs

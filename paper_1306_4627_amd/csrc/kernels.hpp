@@ -95,6 +95,7 @@ struct TbArgs {
     int32_t ckpt_every;
     int32_t nb;                 // tiles per band recomputed together (one per lane)
     int32_t nbands;             // bands per recompute round
+    int32_t ysh;                // stream value >> ysh = symbol code
 };
 
 // Traceback passes over strips (runs of bands of one pair): speculative
@@ -121,13 +122,14 @@ struct EmitArgs {
     uint32_t *error;            // set to 2 when a bitmap disagrees with the length
 };
 
-constexpr int kFillBlock = 256;   // four independent waves per work-group
+constexpr int kFillBlock = 256;   // at most four independent waves per work-group
 constexpr int kTbBlock = 256;
 
 size_t fill_lds_bytes(int wpl, int sigma);
 size_t tb_lds_bytes(int wpl, int sigma, int ckpt_every, int nb, int bands);
 
-const void *fill_symbol(int wpl, bool tb);
+const void *fill_symbol(int wpl, bool tb, bool raw);
+int fill_block(int wpl, int sigma);   // threads per fill work-group
 const void *tb_symbol(int wpl, int ckpt_every);
 
 hipError_t launch_prep(const PrepArgs &a, uint64_t xbytes_n, hipStream_t s);

@@ -10,11 +10,13 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
 #include <vector>
 
+#include "api_internal.hpp"
 #include "kernels.hpp"
 #include "lcs.h"
 #include "plan.hpp"
@@ -43,6 +45,7 @@ struct lcs_ctx {
     int num_cus = 0;
     std::string arch;
     std::map<TuneKey, std::pair<lcs_tuning, float>> tune_cache;   // autotuner results
+    std::mutex mu;   // guards in_use and tune_cache (a request server uses them from its thread)
 };
 
 namespace {
@@ -68,6 +71,7 @@ struct ClassDev {
     uint32_t *plain_ctr = nullptr;     // plain mode: kQueues queue counters per pair
     uint32_t *q_fill = nullptr, *q_spec = nullptr, *q_fix = nullptr, *q_seal = nullptr;
     uint32_t fill_grid = 1, sp_grid = 1, fx_grid = 1, sl_grid = 1;
+    int fill_waves = 4;                // waves per fill work-group
     int nb = 1;                        // traceback tiles per band recomputed together
     int nbands = 1;                    // traceback bands recomputed together
     uint32_t prio_T = 0xffffffffu;     // fill items this long run at raised priority
@@ -98,6 +102,8 @@ struct Carver {
 
 struct lcs_batch {
     lcs_ctx *ctx = nullptr;
+    lcs::BatchHooks hooks;         // stream and memory of server-owned batches
+    bool ext_mem = false;          // device memory came from hooks.alloc
     uint32_t flags = 0;
     int sigma = 0;
     int ckpt = 0;
@@ -244,6 +250,7 @@ static void stats_from_plan(const Plan &p, uint64_t npairs, lcs_batch_stats *out
 
 extern "C" const char *lcs_status_str(int s) {
     switch (s) {
+        case LCS_PENDING: return "pending (queued or running)";
         case LCS_OK: return "ok";
         case LCS_ERR_ARG: return "invalid argument";
         case LCS_ERR_SYMBOL: return "symbol not in alphabet";
@@ -338,8 +345,15 @@ static void free_batch(lcs_batch *b) {
     for (hipEvent_t &e : b->ev)
         if (e) (void)hipEventDestroy(e);
     if (b->dev) {
-        (void)hipFree(b->dev);
-        if (b->ctx) b->ctx->in_use -= b->dev_bytes;
+        if (b->ext_mem) {
+            b->hooks.release(b->hooks.user, b->dev);
+        } else {
+            (void)hipFree(b->dev);
+            if (b->ctx) {
+                std::lock_guard<std::mutex> lk(b->ctx->mu);
+                b->ctx->in_use -= b->dev_bytes;
+            }
+        }
     }
     delete b;
 }
@@ -442,9 +456,9 @@ static size_t carve(lcs_batch *b, char *base) {
 
 // Persistent grid: as many work-groups as can be resident, capped by work.
 static uint32_t resident_grid(lcs_ctx *ctx, const void *fn, size_t lds, uint64_t work_groups,
-                              int cap) {
+                              int cap, int block = kFillBlock) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kFillBlock, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     uint64_t g = (uint64_t)per_cu * (uint64_t)ctx->num_cus;
@@ -455,7 +469,8 @@ static uint32_t resident_grid(lcs_ctx *ctx, const void *fn, size_t lds, uint64_t
 
 static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
                               const lcs_alphabet *alphabet, uint32_t flags,
-                              const lcs_tuning *tuning, lcs_batch **out) {
+                              const lcs_tuning *tuning, lcs_batch **out,
+                              const BatchHooks *hooks = nullptr) {
     if (!ctx || !out) return LCS_ERR_ARG;
     if (flags & ~(uint32_t)(LCS_WANT_TRACEBACK | LCS_USE_GRAPH)) return LCS_ERR_ARG;
     lcs_status st = check_pairs(pairs, count);
@@ -519,7 +534,7 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     b->out_bytes = (flags & LCS_WANT_TRACEBACK) ? oo : 0;
     PlanConfig cfg;
     fill_plan_config(cfg, sigma, flags, tuning);
-    if (sigma > 127 || max_wpl(sigma) == 0) return LCS_ERR_UNSUPPORTED;
+    if (max_wpl(sigma) == 0) return LCS_ERR_UNSUPPORTED;
     if (cfg.wpl && !wpl_fits(sigma, cfg.wpl)) return LCS_ERR_UNSUPPORTED;
     std::string why = build_plan(shapes, cfg, b->plan);
     if (!why.empty()) {
@@ -530,14 +545,23 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     }
     b->ckpt = cfg.ckpt;
     const size_t need = carve(b.get(), nullptr);
-    if (ctx->in_use + need > ctx->budget) return LCS_ERR_NOMEM;
     if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
     void *mem = nullptr;
-    hipError_t e = hipMalloc(&mem, need);
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? LCS_ERR_NOMEM : LCS_ERR_DEVICE;
+    if (hooks && hooks->alloc) {
+        b->hooks = *hooks;
+        mem = hooks->alloc(hooks->user, need);
+        if (!mem) return LCS_ERR_NOMEM;
+        b->ext_mem = true;
+    } else {
+        if (hooks) b->hooks.stream = hooks->stream;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->in_use + need > ctx->budget) return LCS_ERR_NOMEM;
+        hipError_t e = hipMalloc(&mem, need);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? LCS_ERR_NOMEM : LCS_ERR_DEVICE;
+        ctx->in_use += need;
+    }
     b->dev = mem;
     b->dev_bytes = need;
-    ctx->in_use += need;
     carve(b.get(), (char *)mem);
     lcs_batch *bp = b.release();
 
@@ -572,7 +596,7 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
             s_yoff[s] = yoff[sg.pair];
         }
     }
-    hipStream_t st0 = ctx->own_stream;
+    hipStream_t st0 = bp->hooks.stream ? bp->hooks.stream : ctx->own_stream;
     auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
         if (!bytes) return hipSuccess;
         return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st0);
@@ -623,9 +647,13 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         UP(D.fx_s, C.fx_s.data(), C.fx_s.size() * 4);
         UP(D.sl_t, C.sl_t.data(), C.sl_t.size() * 4);
         const int cap = tuning ? tuning->persistent_waves : 0;
-        D.fill_grid = resident_grid(ctx, fill_symbol(C.wpl, cfg.traceback),
-                                    fill_lds_bytes(C.wpl, sigma), (D.nitems + 3) / 4,
-                                    cap > 0 ? (cap + 3) / 4 : 0);
+        {
+            const int fw = fill_block(C.wpl, sigma) / 64;   // waves per fill work-group
+            D.fill_waves = fw;
+            D.fill_grid = resident_grid(ctx, fill_symbol(C.wpl, cfg.traceback, raw_stream(sigma, C.wpl)),
+                                        fill_lds_bytes(C.wpl, sigma), (D.nitems + fw - 1) / fw,
+                                        cap > 0 ? (cap + fw - 1) / fw : 0, 64 * fw);
+        }
         // raised priority for the items within half of the longest
         {
             uint32_t mt = 0;
@@ -784,6 +812,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         ta.ckpt_every = b->ckpt;
         ta.nb = D.nb;
         ta.nbands = D.nbands;
+        ta.ysh = raw_stream(b->sigma, D.wpl) ? 0 : 9 + __builtin_ctz((unsigned)D.wpl);
         ta.mode = mode;
         if (mode == kTbSpec) {
             ta.tk_t = D.sp_t;
@@ -845,7 +874,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
                 fa.item_begin = D.pl_begin[k];
                 fa.item_end = D.pl_end[k];
                 fa.queue = ctr + kQueues * k;
-                uint32_t g = (fa.item_end - fa.item_begin + 3) / 4;
+                uint32_t g = (fa.item_end - fa.item_begin + D.fill_waves - 1) / D.fill_waves;
                 HIP_TRY(launch_fill(D.wpl, tb, fa, g, s));
                 if (tb) {
                     TbArgs ta = tb_args(ci, kTbSpec);
@@ -891,7 +920,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
 static lcs_status launch_pass(lcs_batch *b, bool eager) {
     lcs_ctx *ctx = b->ctx;
     if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
-    hipStream_t s = ctx->stream;
+    hipStream_t s = b->hooks.stream ? b->hooks.stream : ctx->stream;
     if ((b->flags & LCS_USE_GRAPH) && !b->plain && !eager) {
         if (!b->gexec) {
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -928,7 +957,7 @@ static lcs_status finish(lcs_batch *b) {
     if (!b->ran) return LCS_ERR_ARG;
     lcs_ctx *ctx = b->ctx;
     if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipStreamSynchronize(b->hooks.stream ? b->hooks.stream : ctx->stream));
     uint32_t err = 0;
     HIP_TRY(hipMemcpy(&err, b->error, 4, hipMemcpyDeviceToHost));
     if (err) {
@@ -1082,10 +1111,114 @@ extern "C" lcs_status lcs_traceback_batch(lcs_ctx *ctx, const lcs_pair *pairs, u
 // --------------------------------------------------------------------------
 
 // --------------------------------------------------------------------------
+// library-internal batch interface (request server)
+// --------------------------------------------------------------------------
+
+namespace lcs {
+
+lcs_status batch_create(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                        const lcs_alphabet *alphabet, uint32_t flags, const lcs_tuning *tuning,
+                        const BatchHooks *hooks, lcs_batch **out) {
+    return build_batch(ctx, pairs, count, alphabet, flags, tuning, out, hooks);
+}
+
+lcs_status alphabet_check(const lcs_alphabet *a, const uint8_t *x, uint64_t m, const uint8_t *y,
+                          uint64_t n, int *sigma) {
+    uint8_t lut[256];
+    bool valid[256];
+    const lcs_status st = make_lut(a, lut, valid, sigma);
+    if (st) return st;
+    if ((m && !x) || (n && !y)) return LCS_ERR_ARG;
+    if (m > LCS_MAX_LEN || n > LCS_MAX_LEN) return LCS_ERR_TOO_LONG;
+    if (!all_in(x, m, valid) || !all_in(y, n, valid)) return LCS_ERR_SYMBOL;
+    return LCS_OK;
+}
+
+int ctx_device(lcs_ctx *ctx) { return ctx->device; }
+
+lcs_status ctx_reserve(lcs_ctx *ctx, size_t *bytes, void **mem) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const size_t left = ctx->budget > ctx->in_use ? ctx->budget - ctx->in_use : 0;
+    size_t want = *bytes ? *bytes : left / 2;
+    want = (want + 255) & ~(size_t)255;
+    if (want == 0 || want > left) return LCS_ERR_NOMEM;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
+    const hipError_t e = hipMalloc(mem, want);
+    if (e != hipSuccess) {
+        note_error("hipMalloc", e);
+        return dev_err(e);
+    }
+    ctx->in_use += want;
+    *bytes = want;
+    return LCS_OK;
+}
+
+void ctx_unreserve(lcs_ctx *ctx, void *mem, size_t bytes) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    (void)hipFree(mem);
+    ctx->in_use -= bytes;
+}
+
+lcs_status batch_launch(lcs_batch *b) {
+    if (!b) return LCS_ERR_ARG;
+    return launch_pass(b, true);
+}
+
+int batch_query(lcs_batch *b) {
+    if (!b || !b->ran) return LCS_ERR_ARG;
+    const hipError_t e = hipEventQuery(b->ev[3]);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    note_error("hipEventQuery", e);
+    return dev_err(e);
+}
+
+lcs_status batch_results(lcs_batch *b, std::vector<uint64_t> &lens,
+                         std::vector<std::vector<uint8_t>> *strings) {
+    lens.assign(b->npairs, 0);
+    if (!(b->flags & LCS_WANT_TRACEBACK) || !strings) return lcs_batch_lengths(b, lens.data());
+    const uint64_t cap = b->out_off_host[b->npairs];
+    std::vector<uint8_t> arena(cap + 1);
+    std::vector<uint64_t> offs(b->npairs);
+    lcs_status st = lcs_batch_tracebacks(b, arena.data(), cap, offs.data(), lens.data());
+    if (st) return st;
+    strings->assign(b->npairs, {});
+    for (uint64_t k = 0; k < b->npairs; ++k)
+        (*strings)[k].assign(arena.data() + offs[k], arena.data() + offs[k] + lens[k]);
+    return LCS_OK;
+}
+
+}  // namespace lcs
+
+// --------------------------------------------------------------------------
 // autotuner
 // --------------------------------------------------------------------------
 
 static uint32_t ilog2_u64(uint64_t v) { return v ? 63u - (uint32_t)__builtin_clzll(v) : 0u; }
+
+static TuneKey tune_key(const lcs_pair *pairs, uint64_t count, int sigma, uint32_t flags) {
+    uint64_t mm = 0, mn = 0;
+    double cells = 0;
+    for (uint64_t k = 0; k < count; ++k) {
+        mm = std::max<uint64_t>(mm, pairs[k].m);
+        mn = std::max<uint64_t>(mn, pairs[k].n);
+        cells += (double)pairs[k].m * (double)pairs[k].n;
+    }
+    return TuneKey{flags, (uint32_t)sigma, ilog2_u64(count), ilog2_u64(mm), ilog2_u64(mn),
+                   cells >= 1 ? (uint32_t)(4.0 * std::log2(cells)) : 0u};
+}
+
+namespace lcs {
+bool tuning_cached(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count, int sigma, uint32_t flags,
+                   lcs_tuning *out) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto hit = ctx->tune_cache.find(tune_key(pairs, count, sigma, flags));
+    if (hit == ctx->tune_cache.end()) return false;
+    *out = hit->second.first;
+    return true;
+}
+}  // namespace lcs
 
 extern "C" lcs_status lcs_autotune(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
                                    const lcs_alphabet *alphabet, uint32_t flags,
@@ -1099,21 +1232,16 @@ extern "C" lcs_status lcs_autotune(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t
     int sigma = 0;
     st = make_lut(alphabet, lut, valid, &sigma);
     if (st) return st;
-    if (sigma > 127 || max_wpl(sigma) == 0) return LCS_ERR_UNSUPPORTED;
-    uint64_t mm = 0, mn = 0;
-    double cells = 0;
-    for (uint64_t k = 0; k < count; ++k) {
-        mm = std::max<uint64_t>(mm, pairs[k].m);
-        mn = std::max<uint64_t>(mn, pairs[k].n);
-        cells += (double)pairs[k].m * (double)pairs[k].n;
-    }
-    const TuneKey key{flags, (uint32_t)sigma, ilog2_u64(count), ilog2_u64(mm), ilog2_u64(mn),
-                      cells >= 1 ? (uint32_t)(4.0 * std::log2(cells)) : 0u};
-    auto hit = ctx->tune_cache.find(key);
-    if (hit != ctx->tune_cache.end()) {
-        *best = hit->second.first;
-        if (best_ms) *best_ms = hit->second.second;
-        return LCS_OK;
+    if (max_wpl(sigma) == 0) return LCS_ERR_UNSUPPORTED;
+    const TuneKey key = tune_key(pairs, count, sigma, flags);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto hit = ctx->tune_cache.find(key);
+        if (hit != ctx->tune_cache.end()) {
+            *best = hit->second.first;
+            if (best_ms) *best_ms = hit->second.second;
+            return LCS_OK;
+        }
     }
     // one candidate: plan, one untimed pass, then the best of two timed passes
     auto measure = [&](const lcs_tuning &t, float *ms) -> lcs_status {
@@ -1175,7 +1303,10 @@ extern "C" lcs_status lcs_autotune(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t
             if (st) return st;
         }
     }
-    ctx->tune_cache[key] = {cur, cur_ms};
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->tune_cache[key] = {cur, cur_ms};
+    }
     *best = cur;
     if (best_ms) *best_ms = cur_ms;
     return LCS_OK;
@@ -1189,7 +1320,7 @@ static lcs_status plan_only(const uint64_t *m, const uint64_t *n, uint64_t count
     if (flags & ~(uint32_t)(LCS_WANT_TRACEBACK | LCS_USE_GRAPH)) return LCS_ERR_ARG;
     lcs_status st = check_tuning(tuning);
     if (st) return st;
-    if (alphabet_size > 127 || max_wpl(alphabet_size) == 0) return LCS_ERR_UNSUPPORTED;
+    if (max_wpl(alphabet_size) == 0) return LCS_ERR_UNSUPPORTED;
     if (tuning && tuning->words_per_lane && !wpl_fits(alphabet_size, tuning->words_per_lane))
         return LCS_ERR_UNSUPPORTED;
     shapes.resize(count);

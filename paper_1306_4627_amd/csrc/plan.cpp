@@ -13,18 +13,34 @@ static inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b
 // pair: short columns keep all lanes busy with one word each; long columns
 // amortise the per-step overhead over more words per lane.
 //
-// Limits from the kernel: a stream element (code << log2(wpl*512)) must fit
-// 16 bits, so sigma * wpl <= 127; and four waves' match masks, 4 * (sigma+1)
-// * wpl * 512 bytes of LDS, should leave room for a second work-group on the
-// compute unit, so (sigma+1) * wpl <= 40 when possible.
-int max_wpl(int sigma) {
-    for (int w = 8; w >= 1; w >>= 1)
-        if ((sigma + 1) * w <= 40 && sigma * w <= 127) return w;
-    return (sigma * 1 <= 127 && (sigma + 1) * 4 * 512 * 1 <= 160 * 1024) ? 1 : 0;
+// Limits from the kernel: the fill keeps the match masks of its waves in
+// LDS, (sigma+1) * wpl * 512 bytes per wave, with four, two or one waves per
+// work-group, so (sigma+1) * wpl * 512 <= 160 KiB.  The stream element is
+// the code already shifted to its LDS row, code << log2(wpl*512), when that
+// fits 16 bits (sigma * wpl <= 127); otherwise ("raw" stream, wpl 1 or 2)
+// it is the plain code and the fill shifts it.  Where possible the batch
+// keeps (sigma+1) * wpl <= 40, so that a second work-group fits a compute
+// unit.
+bool raw_stream(int sigma, int wpl) { return sigma * wpl > 127; }
+
+int fill_waves(int sigma, int wpl) {
+    const size_t per_wave = (size_t)(sigma + 1) * wpl * 512;
+    for (int w = 4; w >= 1; w >>= 1)
+        if ((size_t)w * per_wave <= 160 * 1024) return w;
+    return 0;
 }
 
 bool wpl_fits(int sigma, int wpl) {
-    return sigma * wpl <= 127 && (size_t)4 * (sigma + 1) * wpl * 512 <= 160 * 1024;
+    if (sigma < 1 || sigma > 256) return false;
+    if (wpl != 1 && wpl != 2 && wpl != 4 && wpl != 8) return false;
+    if (raw_stream(sigma, wpl) && wpl > 2) return false;
+    return fill_waves(sigma, wpl) > 0;
+}
+
+int max_wpl(int sigma) {
+    for (int w = 8; w >= 1; w >>= 1)
+        if ((sigma + 1) * w <= 40 && wpl_fits(sigma, w)) return w;
+    return wpl_fits(sigma, 1) ? 1 : 0;
 }
 
 // One words-per-lane for the whole batch (one fill launch): two words per
@@ -237,7 +253,10 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
 
     // lay out the Y stream: one all-sentinel region per class, then one
     // region per segment
-    auto shift_of = [](int wpl) { return (uint8_t)(9 + (wpl == 1 ? 0 : wpl == 2 ? 1 : wpl == 4 ? 2 : 3)); };
+    auto shift_of = [&](int wpl) {
+        return raw_stream(cfg.sigma, wpl) ? (uint8_t)0
+                                          : (uint8_t)(9 + (wpl == 1 ? 0 : wpl == 2 ? 1 : wpl == 4 ? 2 : 3));
+    };
     uint64_t cursor = 0;
     std::vector<uint64_t> class_sent(out.classes.size(), 0);
     for (size_t ci = 0; ci < out.classes.size(); ++ci) {
@@ -379,7 +398,8 @@ std::string check_plan(const std::vector<PairShape> &pairs, const Plan &p) {
             bool ok = false;
             for (const Segment *sg : sent)
                 if (sg->begin == C.ln_ys[li] && sg->len >= C.it_T[li / kLanes] + kChunk &&
-                    C.ln_skew[li] == 0 && sg->shift == 9 + __builtin_ctz((unsigned)C.wpl))
+                    C.ln_skew[li] == 0 &&
+                    sg->shift == (raw_stream(p.cfg.sigma, C.wpl) ? 0 : 9 + __builtin_ctz((unsigned)C.wpl)))
                     ok = true;
             if (!ok) return "idle lane without a sentinel region";
         }

@@ -115,9 +115,13 @@ constexpr int kMaxChain = 4096;
 inline uint64_t max_rows(int wpl) { return (uint64_t)kMaxChain * kLanes * wpl * 64; }
 
 // Largest words-per-lane the kernels accept for an alphabet size, and
-// whether a given one fits (stream element width and LDS size).
+// whether a given one fits (stream element width and LDS size); whether the
+// stream holds plain codes (alphabets too large for pre-shifted ones); and
+// the fill's waves per work-group.
 int max_wpl(int sigma);
 bool wpl_fits(int sigma, int wpl);
+bool raw_stream(int sigma, int wpl);
+int fill_waves(int sigma, int wpl);
 
 // Build a plan.  Returns an empty string on success, else a reason.
 std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cfg, Plan &out);

@@ -46,9 +46,9 @@ size_t tb_lds_bytes(int wpl, int sigma, int K, int nb, int bands) {
 // reads the mask.
 template <int WPL, int LOGK>
 __device__ __forceinline__ void recompute_tile(uint64_t *dst, const uint64_t *pmd, const uint16_t *yst,
-                                               const uint32_t *cbs, const uint64_t (&V0)[WPL]) {
+                                               const uint32_t *cbs, const uint64_t (&V0)[WPL],
+                                               uint32_t ysh) {
     constexpr uint32_t K = 1u << LOGK;
-    constexpr uint32_t kShift = 9 + (WPL == 1 ? 0 : WPL == 2 ? 1 : WPL == 4 ? 2 : 3);
     uint32_t vlo[WPL], vhi[WPL];
 #pragma unroll
     for (int q = 0; q < WPL; ++q) {
@@ -66,7 +66,7 @@ __device__ __forceinline__ void recompute_tile(uint64_t *dst, const uint64_t *pm
             uint64_t Mg[8][WPL];
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const uint32_t code = ((k & 1) ? (yw[k >> 1] >> 16) : (yw[k >> 1] & 0xffffu)) >> kShift;
+                const uint32_t code = ((k & 1) ? (yw[k >> 1] >> 16) : (yw[k >> 1] & 0xffffu)) >> ysh;
 #pragma unroll
                 for (int q = 0; q < WPL; ++q) Mg[k][q] = pmd[code * WPL + q];
             }
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
     extern __shared__ uint64_t smem[];
     constexpr uint32_t K = 1u << LOGK;
     constexpr uint32_t BAND = 64u * WPL;
-    constexpr uint32_t kShift = 9 + (WPL == 1 ? 0 : WPL == 2 ? 1 : WPL == 4 ? 2 : 3);
+    const uint32_t ysh = (uint32_t)a.ysh;   // stream value -> symbol code
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int32_t sig1 = a.sigma + 1;
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
                             recompute_tile<WPL, LOGK>(tiles + (size_t)lane * SW,
                                                       pm + (size_t)(lane / NB) * sig1 * WPL,
                                                       ystage + (size_t)lane * K,
-                                                      cbstage + (size_t)lane * (K / 32), V0);
+                                                      cbstage + (size_t)lane * (K / 32), V0, ysh);
                         wave_lds_sync();
                         dsl = 0;
                         khi = kt;
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
                             const uint32_t sl = (uint32_t)(dsl * NB + (khi - (tl >> LOGK)));
                             const uint32_t o = (uint32_t)tl & (K - 1);
                             VL = tiles[(size_t)sl * SW + o * WPL + q];
-                            const uint32_t code = (uint32_t)ystage[(size_t)sl * K + o] >> kShift;
+                            const uint32_t code = (uint32_t)ystage[(size_t)sl * K + o] >> ysh;
                             ML = pmd[code * WPL + q];
                         }
                         if (wq0 + q != dwi) {

@@ -17,6 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblcs_hip.so")
 
+LCS_PENDING = 1
 LCS_OK = 0
 LCS_ERR_ARG = -1
 LCS_ERR_SYMBOL = -2
@@ -57,6 +58,21 @@ class lcs_tuning(ctypes.Structure):
                 ("persistent_waves", ctypes.c_int32), ("plain", ctypes.c_int32),
                 ("strip_rows", ctypes.c_int32), ("tb_tiles", ctypes.c_int32),
                 ("tb_bands", ctypes.c_int32)]
+
+
+class lcs_server_config(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_size_t), ("streams", ctypes.c_int32),
+                ("max_batch_pairs", ctypes.c_int32)]
+
+
+class lcs_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "failed", "cancelled",
+                                                "queued", "batches", "max_inflight", "cells",
+                                                "arena_bytes", "arena_peak_bytes", "plan_ns",
+                                                "collect_ns", "device_ns")]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class lcs_batch_stats(ctypes.Structure):
@@ -127,6 +143,22 @@ def _load() -> ctypes.CDLL:
     lib.lcs_autotune.argtypes = [vp, P(lcs_pair), u64, P(lcs_alphabet), ctypes.c_uint32,
                                  P(lcs_tuning), P(ctypes.c_float)]
     lib.lcs_autotune.restype = i32
+    lib.lcs_server_create.argtypes = [vp, P(lcs_server_config), P(vp)]
+    lib.lcs_server_create.restype = i32
+    lib.lcs_server_destroy.argtypes = [vp]
+    lib.lcs_server_destroy.restype = None
+    lib.lcs_submit.argtypes = [vp, u8p, u64, u8p, u64, P(lcs_alphabet), i32, u64p]
+    lib.lcs_submit.restype = i32
+    lib.lcs_poll.argtypes = [vp, u64]
+    lib.lcs_poll.restype = i32
+    lib.lcs_wait.argtypes = [vp, u64, ctypes.c_int64]
+    lib.lcs_wait.restype = i32
+    lib.lcs_result.argtypes = [vp, u64, u64p, u8p, u64, u64p]
+    lib.lcs_result.restype = i32
+    lib.lcs_cancel.argtypes = [vp, u64]
+    lib.lcs_cancel.restype = i32
+    lib.lcs_server_stats_get.argtypes = [vp, P(lcs_server_stats)]
+    lib.lcs_server_stats_get.restype = i32
     lib.lcs_plan_describe.argtypes = [u64p, u64p, u64, ctypes.c_uint16, ctypes.c_uint32,
                                       P(lcs_tuning), P(lcs_batch_stats)]
     lib.lcs_plan_describe.restype = i32
@@ -356,6 +388,78 @@ class Batch:
     def close(self) -> None:
         if getattr(self, "h", None):
             _lib.lcs_batch_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The request server (``lcs_server_*``): submit single requests at any
+    time; a dispatcher thread in the library batches and runs them."""
+
+    def __init__(self, ctx: Context, mem_budget_bytes: int = 0, streams: int = 0,
+                 max_batch_pairs: int = 0):
+        self.ctx = ctx
+        cfg = lcs_server_config(int(mem_budget_bytes), int(streams), int(max_batch_pairs))
+        h = ctypes.c_void_p()
+        _check(_lib.lcs_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)), "lcs_server_create")
+        self.h = h
+        self._alphas = {}
+        self._cap = {}
+
+    def submit(self, x, y, alphabet="dna", traceback: bool = False) -> int:
+        xa, ya = _as_u8(x), _as_u8(y)
+        key = alphabet if isinstance(alphabet, (str, bytes)) else id(alphabet)
+        al = self._alphas.get(key)
+        if al is None:
+            al = self._alphas[key] = _alpha(alphabet)
+        t = ctypes.c_uint64(0)
+        _check(_lib.lcs_submit(self.h, _u8p(xa), xa.size, _u8p(ya), ya.size, ctypes.byref(al.c),
+                               int(bool(traceback)), ctypes.byref(t)), "lcs_submit")
+        self._cap[t.value] = (bool(traceback), min(xa.size, ya.size) if traceback else 0)
+        return t.value
+
+    def poll(self, ticket: int) -> int:
+        return int(_lib.lcs_poll(self.h, ticket))
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> int:
+        return int(_lib.lcs_wait(self.h, ticket, int(timeout_us)))
+
+    def result(self, ticket: int):
+        """(length, LCS bytes or None, latency in ns) of a finished request."""
+        tb, cap = self._cap.get(ticket, (False, 0))
+        buf = np.empty(max(cap, 1), dtype=np.uint8)
+        L = ctypes.c_uint64(0)
+        lat = ctypes.c_uint64(0)
+        st = int(_lib.lcs_result(self.h, ticket, ctypes.byref(L), _u8p(buf), cap, ctypes.byref(lat)))
+        if st == LCS_PENDING:
+            raise LcsError(st, "lcs_result")
+        self._cap.pop(ticket, None)
+        _check(st, "lcs_result")
+        s = buf[: L.value].tobytes() if tb else None
+        return int(L.value), s, int(lat.value)
+
+    def cancel(self, ticket: int) -> int:
+        return int(_lib.lcs_cancel(self.h, ticket))
+
+    def stats(self) -> dict:
+        st = lcs_server_stats()
+        _check(_lib.lcs_server_stats_get(self.h, ctypes.byref(st)), "lcs_server_stats_get")
+        return st.as_dict()
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            _lib.lcs_server_destroy(self.h)
             self.h = None
 
     def __enter__(self):

@@ -29,7 +29,7 @@ def test_header_symbols_are_exported():
 
 def test_status_strings_and_version():
     assert lcs.status_str(0) == "ok"
-    for code in range(-7, 0):
+    for code in range(-7, 2):
         assert lcs.status_str(code) and lcs.status_str(code) != "unknown status"
     assert lcs.status_str(-99) == "unknown status"
     assert "gfx950" in lcs.version()
@@ -52,6 +52,21 @@ def test_autotune_arguments_rejected_before_any_device_call():
     best = lcs.lcs_tuning()
     al = lcs.lcs_alphabet(4, ctypes.cast(ctypes.c_char_p(b"ACGT"), ctypes.POINTER(ctypes.c_uint8)))
     assert L.lcs_autotune(None, None, 0, ctypes.byref(al), 0, ctypes.byref(best), None) == lcs.LCS_ERR_ARG
+
+
+def test_server_arguments_rejected_before_any_device_call():
+    L = lcs.lib()
+    h = ctypes.c_void_p()
+    assert L.lcs_server_create(None, None, ctypes.byref(h)) == lcs.LCS_ERR_ARG
+    t = ctypes.c_uint64(0)
+    al = lcs.lcs_alphabet(4, ctypes.cast(ctypes.c_char_p(b"ACGT"), ctypes.POINTER(ctypes.c_uint8)))
+    assert L.lcs_submit(None, None, 0, None, 0, ctypes.byref(al), 0, ctypes.byref(t)) == lcs.LCS_ERR_ARG
+    assert L.lcs_poll(None, 1) == lcs.LCS_ERR_ARG
+    assert L.lcs_wait(None, 1, 0) == lcs.LCS_ERR_ARG
+    assert L.lcs_cancel(None, 1) == lcs.LCS_ERR_ARG
+    assert L.lcs_result(None, 1, ctypes.byref(t), None, 0, None) == lcs.LCS_ERR_ARG
+    assert lcs.status_str(lcs.LCS_PENDING).startswith("pending")
+    L.lcs_server_destroy(None)
 
 
 def test_null_arguments_rejected_before_any_device_call():
@@ -78,11 +93,21 @@ def test_plan_rejects_bad_tuning_and_alphabets():
         lcs.plan_describe(m, n, 4, traceback=True, ckpt_interval=100)
     assert e.value.status == lcs.LCS_ERR_ARG
     with pytest.raises(lcs.LcsError) as e:
-        lcs.plan_describe(m, n, 200)
+        lcs.plan_describe(m, n, 200, words_per_lane=4)   # plain codes: one or two words per lane
+    assert e.value.status == lcs.LCS_ERR_UNSUPPORTED
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.plan_describe(m, n, 256, words_per_lane=2)   # 257 x 1 KiB of match masks per wave
     assert e.value.status == lcs.LCS_ERR_UNSUPPORTED
     with pytest.raises(lcs.LcsError) as e:
         lcs.plan_describe(m, n, 20, words_per_lane=8)
     assert e.value.status == lcs.LCS_ERR_UNSUPPORTED
+    # every alphabet size up to all 256 bytes is planned (one word per lane
+    # at the largest sizes)
+    for sigma in (1, 4, 20, 79, 80, 127, 128, 159, 200, 256):
+        d = lcs.plan_describe(m, n, sigma, traceback=True)
+        assert d["words_per_lane"] >= 1
+        assert lcs.plan_selfcheck([1, 64, 700, 5000, 70000], [9, 64, 800, 4000, 100], sigma,
+                                  traceback=True) == 0
     with pytest.raises(lcs.LcsError) as e:
         lcs.plan_describe([1 << 40], [5], 4)
     assert e.value.status == lcs.LCS_ERR_TOO_LONG

@@ -72,6 +72,33 @@ def test_single_pairs_edge_lengths(ctx, lcs, alname):
             assert lcs.lcs_traceback(ctx, x, y, al) == oracle.lcs_traceback(x, y), (m, n)
 
 
+@pytest.mark.parametrize("sigma,wpl", [(80, 1), (128, 1), (150, 2), (200, 1), (256, 1), (256, 0)])
+def test_wide_alphabets(ctx, lcs, sigma, wpl):
+    # alphabets past 127 symbols: the stream holds plain codes and the fill
+    # runs fewer waves per work-group; the byte order of the alphabet is
+    # shuffled so that codes differ from byte values
+    g = inputs.rng(6050 + sigma + wpl)
+    syms = bytes(int(v) for v in g.permutation(256)[:sigma])
+    pairs = []
+    for m in (0, 1, 63, 64, 65, 300, 2000, 5000):
+        for n in (0, 1, 64, 129, 1500):
+            pairs.append((inputs.random_seq(g, m, syms), inputs.random_seq(g, n, syms)))
+    for _ in range(6):
+        x = inputs.random_seq(g, int(g.integers(100, 9000)), syms)
+        y, _ = inputs.mutate(g, x, float(g.uniform(0.05, 0.3)), syms)
+        pairs.append((x, y))
+    _say(f"wide alphabet sigma={sigma} wpl={wpl} pairs={len(pairs)}")
+    al = None if sigma == 256 and wpl == 0 else syms     # None: all 256 bytes in byte order
+    with lcs.Batch(ctx, pairs, al, traceback=True, words_per_lane=wpl) as b:
+        b.run()
+        L = b.lengths()
+        S = b.tracebacks()
+    assert np.array_equal(L, _oracle_lengths(pairs))
+    assert S == _oracle_tracebacks(pairs)
+    p0 = pairs[-1]
+    assert lcs.lcs_traceback(ctx, p0[0], p0[1], al) == oracle.lcs_traceback(p0[0], p0[1])
+
+
 @pytest.mark.parametrize("wpl", [1, 2, 4, 8])
 def test_batch_edge_lengths_lengths_and_tracebacks(ctx, lcs, wpl):
     g = inputs.rng(6000 + wpl)
