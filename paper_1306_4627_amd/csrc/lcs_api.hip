@@ -45,7 +45,8 @@ struct lcs_ctx {
     int num_cus = 0;
     std::string arch;
     std::map<TuneKey, std::pair<lcs_tuning, float>> tune_cache;   // autotuner results
-    std::mutex mu;   // guards in_use and tune_cache (a request server uses them from its thread)
+    std::map<std::tuple<const void *, int, size_t>, int> occupancy;   // kernel, block, LDS -> groups per CU
+    std::mutex mu;   // guards in_use, tune_cache and occupancy (a request server uses them from its thread)
 };
 
 namespace {
@@ -116,6 +117,8 @@ struct lcs_batch {
     uint64_t out_bytes = 0;
     void *dev = nullptr;
     size_t dev_bytes = 0;
+    size_t upload_bytes = 0;       // host-written prefix of the allocation
+    size_t readback_bytes = 0;     // lengths, error word and strings, from out_len
     uint8_t *lut = nullptr, *xbytes = nullptr, *xcodes = nullptr, *ybytes = nullptr;
     uint64_t xarena = 0, yarena = 0;
     uint64_t *pair_xoff = nullptr, *pair_yoff = nullptr, *pair_out = nullptr, *out_len = nullptr;
@@ -364,14 +367,13 @@ static size_t carve(lcs_batch *b, char *base) {
     cv.base = base;
     const Plan &p = b->plan;
     const uint64_t np = b->npairs;
+    // ---- written from the host (one upload of [0, upload_bytes)) ----
     b->lut = cv.take<uint8_t>(256);
     b->xbytes = cv.take<uint8_t>(b->xarena + 64);
-    b->xcodes = cv.take<uint8_t>(b->xarena + 64);
     b->ybytes = cv.take<uint8_t>(b->yarena + 64);
     b->pair_xoff = cv.take<uint64_t>(np + 1);
     b->pair_yoff = cv.take<uint64_t>(np + 1);
     b->pair_out = cv.take<uint64_t>(np + 1);
-    b->out_len = cv.take<uint64_t>(np + 1);
     b->pair_diag = cv.take<uint64_t>(np + 1);
     b->em_pair = cv.take<uint32_t>(b->em_pair_host.size() + 1);
     b->em_w0 = cv.take<uint32_t>(b->em_w0_host.size() + 1);
@@ -384,29 +386,7 @@ static size_t carve(lcs_batch *b, char *base) {
     b->seg_n = cv.take<uint32_t>(ns + 1);
     b->seg_pre = cv.take<uint32_t>(ns + 1);
     b->seg_shift = cv.take<uint8_t>(ns + 1);
-    b->ystream = cv.take<uint16_t>(p.ys_elems + 64);
-    b->out = cv.take<uint8_t>(b->out_bytes + 64);
-    // zeroed before every pass, 32-bit: error word, then per class the fill
-    // and traceback queue counters and (plain mode) two counters per pair
     b->cls.resize(p.classes.size());
-    uint64_t nz = 1;
-    for (size_t ci = 0; ci < p.classes.size(); ++ci) {
-        const ClassPlan &C = p.classes[ci];
-        nz += kQueues;
-        if (b->plain) nz += kQueues * C.tb_pair.size();
-    }
-    b->zero = cv.take<uint32_t>(nz);
-    b->nzero = nz;
-    b->error = b->zero;
-    // zeroed before every pass, 64-bit: traceback bitmaps, then the carry
-    // hand-over words of every class
-    uint64_t nz64 = (b->flags & LCS_WANT_TRACEBACK) ? b->diag_words : 0;
-    for (const ClassPlan &C : p.classes) nz64 += C.xf_words;
-    b->zero64 = cv.take<uint64_t>(nz64 + 1);
-    b->nzero64 = nz64;
-    b->diag = b->zero64;
-    uint64_t z64 = (b->flags & LCS_WANT_TRACEBACK) ? b->diag_words : 0;
-    uint64_t zc = 1;
     for (size_t ci = 0; ci < p.classes.size(); ++ci) {
         const ClassPlan &C = p.classes[ci];
         ClassDev &D = b->cls[ci];
@@ -437,6 +417,39 @@ static size_t carve(lcs_batch *b, char *base) {
         D.fx_t = cv.take<uint32_t>(D.nfx + 1);
         D.fx_s = cv.take<uint32_t>(D.nfx + 1);
         D.sl_t = cv.take<uint32_t>(D.nsl + 1);
+    }
+    cv.off = (cv.off + 255) & ~(size_t)255;
+    b->upload_bytes = cv.off;
+    // ---- read back after a pass (one copy of [out_len, end of out)) ----
+    b->out_len = cv.take<uint64_t>(np + 1);
+    // zeroed before every pass, 32-bit: error word, then per class the fill
+    // and traceback queue counters and (plain mode) kQueues counters per pair
+    uint64_t nz = 1;
+    for (size_t ci = 0; ci < p.classes.size(); ++ci) {
+        const ClassPlan &C = p.classes[ci];
+        nz += kQueues;
+        if (b->plain) nz += kQueues * C.tb_pair.size();
+    }
+    b->zero = cv.take<uint32_t>(nz);
+    b->nzero = nz;
+    b->error = b->zero;
+    b->out = cv.take<uint8_t>(b->out_bytes + 64);
+    b->readback_bytes = (size_t)((char *)(b->out + b->out_bytes) - (char *)b->out_len);
+    // ---- device only ----
+    b->xcodes = cv.take<uint8_t>(b->xarena + 64);
+    b->ystream = cv.take<uint16_t>(p.ys_elems + 64);
+    // zeroed before every pass, 64-bit: traceback bitmaps, then the carry
+    // hand-over words of every class
+    uint64_t nz64 = (b->flags & LCS_WANT_TRACEBACK) ? b->diag_words : 0;
+    for (const ClassPlan &C : p.classes) nz64 += C.xf_words;
+    b->zero64 = cv.take<uint64_t>(nz64 + 1);
+    b->nzero64 = nz64;
+    b->diag = b->zero64;
+    uint64_t z64 = (b->flags & LCS_WANT_TRACEBACK) ? b->diag_words : 0;
+    uint64_t zc = 1;
+    for (size_t ci = 0; ci < p.classes.size(); ++ci) {
+        const ClassPlan &C = p.classes[ci];
+        ClassDev &D = b->cls[ci];
         D.cross = cv.take<uint32_t>(C.n_bands + 1);
         D.strip_res = cv.take<uint32_t>(2 * C.n_strips + 2);
         D.ckpt = cv.take<uint64_t>(C.ck_words + 1);
@@ -458,9 +471,18 @@ static size_t carve(lcs_batch *b, char *base) {
 static uint32_t resident_grid(lcs_ctx *ctx, const void *fn, size_t lds, uint64_t work_groups,
                               int cap, int block = kFillBlock) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->occupancy.find(std::make_tuple(fn, block, lds));
+        if (it != ctx->occupancy.end()) per_cu = it->second;
+    }
+    if (per_cu == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->occupancy[std::make_tuple(fn, block, lds)] = per_cu;
+    }
     uint64_t g = (uint64_t)per_cu * (uint64_t)ctx->num_cus;
     if (cap > 0) g = std::min<uint64_t>(g, (uint64_t)cap);
     g = std::min<uint64_t>(g, std::max<uint64_t>(work_groups, 1));
@@ -570,10 +592,13 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         free_batch(bp);
         return s;
     };
-    std::vector<uint8_t> hx(xa + 64, 0), hy(ya + 64, 0);
+    // the host image of [0, upload_bytes): every host-written region at its
+    // device offset, sent with one copy
+    std::vector<uint8_t> image(bp->upload_bytes, 0);
+    char *const dev0 = (char *)bp->dev;
     for (uint64_t k = 0; k < count; ++k) {
-        if (pairs[k].m) std::memcpy(hx.data() + xoff[k], pairs[k].x, pairs[k].m);
-        if (pairs[k].n) std::memcpy(hy.data() + yoff[k], pairs[k].y, pairs[k].n);
+        if (pairs[k].m) std::memcpy(image.data() + (bp->xbytes - (uint8_t *)dev0) + xoff[k], pairs[k].x, pairs[k].m);
+        if (pairs[k].n) std::memcpy(image.data() + (bp->ybytes - (uint8_t *)dev0) + yoff[k], pairs[k].y, pairs[k].n);
     }
     std::vector<uint32_t> hm(count + 1, 0), hn(count + 1, 0);
     for (uint64_t k = 0; k < count; ++k) {
@@ -599,7 +624,10 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     hipStream_t st0 = bp->hooks.stream ? bp->hooks.stream : ctx->own_stream;
     auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
         if (!bytes) return hipSuccess;
-        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st0);
+        const size_t off = (size_t)((char *)dst - dev0);
+        if (off + bytes > image.size()) return hipErrorInvalidValue;
+        std::memcpy(image.data() + off, src, bytes);
+        return hipSuccess;
     };
 #define UP(dst, src, bytes)                          \
     do {                                             \
@@ -607,8 +635,6 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         if (e_ != hipSuccess) return fail(dev_err(e_)); \
     } while (0)
     UP(bp->lut, lut, 256);
-    UP(bp->xbytes, hx.data(), xa + 64);
-    UP(bp->ybytes, hy.data(), ya + 64);
     UP(bp->pair_xoff, xoff.data(), count * 8);
     UP(bp->pair_yoff, yoff.data(), count * 8);
     UP(bp->pair_out, bp->out_off_host.data(), count * 8);
@@ -710,6 +736,9 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         }
     }
 #undef UP
+    if (bp->upload_bytes &&
+        hipMemcpyAsync(bp->dev, image.data(), bp->upload_bytes, hipMemcpyHostToDevice, st0) != hipSuccess)
+        return fail(LCS_ERR_DEVICE);
     if (hipStreamSynchronize(st0) != hipSuccess) return fail(LCS_ERR_DEVICE);
     for (hipEvent_t &ev : bp->ev)
         if (hipEventCreate(&ev) != hipSuccess) return fail(LCS_ERR_DEVICE);
@@ -969,11 +998,36 @@ static lcs_status finish(lcs_batch *b) {
     return LCS_OK;
 }
 
+// Wait for the last pass and copy its results to the host in one piece:
+// the lengths and the error word, and with `strings` also the LCS bytes (the
+// three regions are adjacent on the device).  LCS_ERR_DEVICE if a kernel set
+// the error word.
+static lcs_status readback(lcs_batch *b, bool strings, std::vector<uint8_t> &host) {
+    if (!b->ran) return LCS_ERR_ARG;
+    lcs_ctx *ctx = b->ctx;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
+    HIP_TRY(hipStreamSynchronize(b->hooks.stream ? b->hooks.stream : ctx->stream));
+    const size_t err_off = (size_t)((char *)b->error - (char *)b->out_len);
+    const size_t bytes = strings ? std::max(b->readback_bytes, err_off + 4) : err_off + 4;
+    host.resize(bytes);
+    HIP_TRY(hipMemcpy(host.data(), b->out_len, bytes, hipMemcpyDeviceToHost));
+    uint32_t err = 0;
+    std::memcpy(&err, host.data() + err_off, 4);
+    if (err) {
+        std::snprintf(g_last_error, sizeof g_last_error, "kernel error flag %u (%s)", err,
+                      (err & 1u) ? "a carry hand-over wait ran out of polls"
+                                 : "a traceback disagrees with its length");
+        return LCS_ERR_DEVICE;
+    }
+    return LCS_OK;
+}
+
 extern "C" lcs_status lcs_batch_lengths(lcs_batch *b, uint64_t *out_lens) {
     if (!b || (b->npairs && !out_lens)) return LCS_ERR_ARG;
-    lcs_status st = finish(b);
+    std::vector<uint8_t> host;
+    lcs_status st = readback(b, false, host);
     if (st) return st;
-    if (b->npairs) HIP_TRY(hipMemcpy(out_lens, b->out_len, b->npairs * 8, hipMemcpyDeviceToHost));
+    if (b->npairs) std::memcpy(out_lens, host.data(), b->npairs * 8);
     return LCS_OK;
 }
 
@@ -984,18 +1038,17 @@ extern "C" lcs_status lcs_batch_tracebacks(lcs_batch *b, uint8_t *out_arena, uin
     if (b->npairs && (!out_offsets || !out_lens)) return LCS_ERR_ARG;
     if (arena_cap < b->out_off_host[b->npairs]) return LCS_ERR_BUFFER;
     if (b->out_off_host[b->npairs] && !out_arena) return LCS_ERR_ARG;
-    lcs_status st = finish(b);
+    std::vector<uint8_t> host;
+    lcs_status st = readback(b, true, host);
     if (st) return st;
-    std::vector<uint64_t> L(b->npairs);
-    std::vector<uint8_t> raw(b->out_bytes + 1);
-    if (b->npairs) HIP_TRY(hipMemcpy(L.data(), b->out_len, b->npairs * 8, hipMemcpyDeviceToHost));
-    if (b->out_bytes) HIP_TRY(hipMemcpy(raw.data(), b->out, b->out_bytes, hipMemcpyDeviceToHost));
+    const uint64_t *L = (const uint64_t *)host.data();
+    const uint8_t *raw = host.data() + ((char *)b->out - (char *)b->out_len);
     uint64_t o = 0;
     for (uint64_t k = 0; k < b->npairs; ++k) {
         if (L[k] > std::min(b->m[k], b->n[k])) return LCS_ERR_DEVICE;
         out_offsets[k] = o;
         out_lens[k] = L[k];
-        if (L[k]) std::memcpy(out_arena + o, raw.data() + b->out_off_host[k], L[k]);
+        if (L[k]) std::memcpy(out_arena + o, raw + b->out_off_host[k], L[k]);
         o += L[k];
     }
     return LCS_OK;
