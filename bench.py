@@ -150,6 +150,36 @@ def serve_leg(lcs, ctx, rates, count: int):
     return out
 
 
+# Table-1 of the paper: (M, N) -> speedup on its four-processor system
+PAPER_TABLE1_SPEEDUP = {(5000, 200): 3.22, (10000, 1500): 2.89}
+
+
+def striped_leg(lcs, ctx, cores: int):
+    """The paper's row-striped OpenMP method on this host at Table-1 shapes
+    and at 4096 x 4096, on 1, 4 and all threads, beside one GPU pass over the
+    same single pair (length + traceback, inputs resident)."""
+    from paper_1306_4627_amd import inputs
+    from paper_1306_4627_amd.striped import striped_lcs
+    g = inputs.rng(61)
+    rows = []
+    for m, n in ((5000, 200), (10000, 1500), (4096, 4096)):
+        x = inputs.random_seq(g, m, inputs.DNA)
+        y = inputs.random_seq(g, n, inputs.DNA)
+        ms = {}
+        for t in sorted({1, 4, cores}):
+            ms[t] = min(striped_lcs(x, y, t, 64)[3] for _ in range(3)) * 1e3
+        with lcs.Batch(ctx, [(x, y)], "dna", traceback=True, words_per_lane=1) as b:
+            b.time(eager=True)
+            gpu = min(b.time(eager=True)[0] for _ in range(3))
+        rows.append({"m": m, "n": n, "cpu_ms": {str(k): round(v, 3) for k, v in ms.items()},
+                     "speedup_4_threads": round(ms[1] / ms[4], 2),
+                     "paper_speedup_4_processors": PAPER_TABLE1_SPEEDUP.get((m, n)),
+                     "gpu_pass_ms": round(gpu, 3),
+                     "gpu_over_best_cpu": round(min(ms.values()) / gpu, 1)})
+        log(f"striped {m}x{n}: {rows[-1]}")
+    return rows
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +297,8 @@ def main() -> int:
                           "rates": serve_leg(lcs, ctx, (1000, 8000, 64000), args.serve_requests)}
     if not args.no_cpu:
         threads = min(len(os.sched_getaffinity(0)), 16)
+        log(f"paper's striped OpenMP method on the host ({threads} threads)")
+        out["paper_striped_host"] = striped_leg(lcs, ctx, threads)
         log(f"cpu oracle leg ({threads} threads)")
         cb = cpu_baseline(ps, tb, args.cpu_cells, threads)
         out["cpu_baseline"] = cb

@@ -46,5 +46,22 @@ def build_library(verbose: bool = False) -> str:
     return LIB
 
 
+STRIPED_SRC = os.path.join(HERE, "host", "striped.c")
+STRIPED_LIB = os.path.join(HERE, "libstriped.so")
+
+
+def build_striped() -> str:
+    """The host baseline of the paper's row-striped OpenMP method."""
+    tmp = STRIPED_LIB + ".tmp"
+    cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
+           "-o", tmp, STRIPED_SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("gcc failed for striped.c:\n" + r.stdout + r.stderr)
+    os.replace(tmp, STRIPED_LIB)
+    return STRIPED_LIB
+
+
 if __name__ == "__main__":
     print(build_library(verbose=True))
+    print(build_striped())
