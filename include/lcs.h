@@ -82,6 +82,12 @@ typedef struct lcs_batch lcs_batch;
 /* Batch flags. */
 #define LCS_WANT_TRACEBACK 1u   /* also recover the canonical LCS of each pair */
 #define LCS_USE_GRAPH      2u   /* replay the launch sequence as a HIP graph */
+#define LCS_THRESHOLD      4u   /* threshold pass (lcs_batch_set_threshold); not
+                                   with LCS_WANT_TRACEBACK */
+
+/* Length reported for a pair whose threshold answer came before its last
+ * column (the fill of that pair stopped early). */
+#define LCS_LENGTH_UNKNOWN UINT64_MAX
 
 /* Tuning knobs; a zero field means "choose automatically".
  *  words_per_lane  : 64-bit words of the bit-vector column held per lane
@@ -182,7 +188,8 @@ lcs_status lcs_traceback_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t cou
 
 /* Plan and upload a batch without running it.  The input bytes are copied to
  * device memory; the caller's host buffers may be released afterwards.
- * flags: LCS_WANT_TRACEBACK | LCS_USE_GRAPH.  tuning may be NULL (automatic).
+ * flags: LCS_WANT_TRACEBACK | LCS_USE_GRAPH | LCS_THRESHOLD.  tuning may be
+ * NULL (automatic).
  * Fails with LCS_ERR_NOMEM when the batch would exceed the context budget. */
 lcs_status lcs_batch_create(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
                             const lcs_alphabet *alphabet, uint32_t flags,
@@ -216,6 +223,48 @@ lcs_status lcs_batch_time(lcs_batch *batch, int eager, float *total_ms, float *f
 /* Release a batch (NULL is ignored). */
 void lcs_batch_destroy(lcs_batch *batch);
 
+/* ---- derived outputs (section II) -----------------------------------------
+ *
+ * Section II asks whether a child sequence carries the characteristics of
+ * its parent, and by what percentage.  Here X is the parent and Y the child,
+ * and the similarity of a pair is the share of the parent its LCS keeps:
+ * (100 * L) / m in double precision (the product is exact; one rounding in
+ * the division), and 100 when m == 0.  The yes/no form asks whether the
+ * similarity is at least a given percentage; it is settled as soon as the
+ * partial columns prove it either way, so the fill of such a pair stops
+ * early (lengths are then not known).  Each pair's answer depends on the
+ * pair alone and is exact: it equals the comparison made on the full
+ * length. */
+
+/* Similarity percentages of `count` pairs (out_percent[k] for pairs[k]),
+ * from their exact lengths.  Blocks until done. */
+lcs_status lcs_similarity_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                                const lcs_alphabet *alphabet, double *out_percent);
+
+/* Threshold answers of `count` pairs: out_pass[k] = 1 when the similarity of
+ * pairs[k] is at least min_percent (0 <= min_percent <= 100, LCS_ERR_ARG
+ * otherwise, NaN included), else 0.  out_len (may be NULL) receives each
+ * pair's length when its fill ran to the last column, LCS_LENGTH_UNKNOWN when
+ * the answer came earlier.  Blocks until done. */
+lcs_status lcs_threshold_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                               const lcs_alphabet *alphabet, double min_percent,
+                               uint8_t *out_pass, uint64_t *out_len);
+
+/* Set the threshold of a batch created with LCS_THRESHOLD (required before
+ * its first run; may be changed between runs).  Each pair's target length
+ * -- the least L whose similarity reaches min_percent -- is computed on the
+ * host in double precision and copied to the device on the batch's stream.
+ * LCS_ERR_ARG for a batch without LCS_THRESHOLD or min_percent outside
+ * [0, 100]. */
+lcs_status lcs_batch_set_threshold(lcs_batch *batch, double min_percent);
+
+/* Wait for the batch's last run and copy its threshold answers (out_pass,
+ * input order, 1 = reaches the threshold) and lengths (out_len, may be NULL;
+ * LCS_LENGTH_UNKNOWN for pairs answered before their last column).
+ * LCS_ERR_ARG for a batch without LCS_THRESHOLD.  lcs_batch_lengths on such
+ * a batch reports the same lengths. */
+lcs_status lcs_batch_decisions(lcs_batch *batch, uint8_t *out_pass, uint64_t *out_len);
+
 /* Timed search for the tuning of a batch (the batched form's autotuner).
  * Plans and runs the batch (flags as for lcs_batch_create) under candidate
  * tunings -- words_per_lane 1, 2, 4, 8 as the alphabet allows, then with
@@ -228,7 +277,8 @@ void lcs_batch_destroy(lcs_batch *batch);
  * quarters, of the total cells); a later call with a batch of the same shape
  * returns it without running anything.  Candidates that do not fit the
  * memory budget are skipped; LCS_ERR_NOMEM if none fits.  Argument and
- * symbol errors as for lcs_batch_create. */
+ * symbol errors as for lcs_batch_create; LCS_THRESHOLD is not accepted
+ * (tune the lengths-only shape and pass its tuning to lcs_batch_create). */
 lcs_status lcs_autotune(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
                         const lcs_alphabet *alphabet, uint32_t flags, lcs_tuning *best,
                         float *best_ms);

@@ -14,6 +14,8 @@ from .oracle import (  # noqa: F401
     brute_force_all_lcs,
     recursive_length,
     is_subsequence,
+    similarity_percent,
+    threshold_pass,
     DIAG,
     UP,
     LEFT,

@@ -129,6 +129,27 @@ def lcs_traceback_ckpt(x, y, rows_per_block: int = 512) -> bytes:
 
 
 # ---------------------------------------------------------------------------
+# Derived outputs of section II: how much of the parent the child keeps.
+# ---------------------------------------------------------------------------
+
+def similarity_percent(x, y) -> float:
+    """Section II asks whether the child (Y) carries the parent's (X)
+    characteristics and by what percentage.  Reading: the share of the parent
+    kept by the LCS, 100 * L / |X|, evaluated in double as (100 * L) / m
+    (the product is exact).  An empty parent is kept whole: 100."""
+    m = len(x)
+    if m == 0:
+        return 100.0
+    return (100.0 * lcs_length(x, y)) / float(m)
+
+
+def threshold_pass(x, y, min_percent: float) -> bool:
+    """Section II's yes/no question for a threshold: does the child keep at
+    least ``min_percent`` of the parent, i.e. similarity_percent >= it."""
+    return similarity_percent(x, y) >= float(min_percent)
+
+
+# ---------------------------------------------------------------------------
 # Exponential reference methods for tiny inputs (pure Python).
 # ---------------------------------------------------------------------------
 

@@ -29,16 +29,17 @@ namespace lcs {
 // which the order below provides with independent instructions: inside a
 // word the low-half bitop3 and the high-half AND sit between the two adds;
 // across words the high-half bitop3 of the previous word and the low-half
-// AND of the next one do.  In the fill the carry mask coming in is written
-// by scalar instructions and the one going out is only read by scalar
-// instructions, which need no wait states; a caller that writes the mask
-// coming in with a VALU instruction puts two wait states after it.
+// AND of the next one do.  The compiler cannot see into an asm statement and
+// pads every boundary between two of them that pass the mask with a wait
+// state, so words go two to a statement.  In the fill the carry mask coming
+// in is written by scalar instructions and the one going out is only read by
+// scalar instructions, which need no wait states; a caller that writes the
+// mask coming in with a VALU instruction puts two wait states after it.
 template <int WPL>
 __device__ __forceinline__ void column_step(uint32_t (&vlo)[WPL], uint32_t (&vhi)[WPL],
                                             const uint64_t (&M)[WPL], uint64_t &carry) {
-#pragma unroll
-    for (int q = 0; q < WPL; ++q) {
-        const uint32_t mlo = (uint32_t)M[q], mhi = (uint32_t)(M[q] >> 32);
+    if constexpr (WPL == 1) {
+        const uint32_t mlo = (uint32_t)M[0], mhi = (uint32_t)(M[0] >> 32);
         uint32_t t0, t1;
         asm("v_and_b32 %[ulo], %[vlo], %[mlo]\n\t"
             "v_addc_co_u32 %[ulo], %[c], %[vlo], %[ulo], %[c]\n\t"
@@ -46,9 +47,31 @@ __device__ __forceinline__ void column_step(uint32_t (&vlo)[WPL], uint32_t (&vhi
             "v_and_b32 %[uhi], %[vhi], %[mhi]\n\t"
             "v_addc_co_u32 %[uhi], %[c], %[vhi], %[uhi], %[c]\n\t"
             "v_bitop3_b32 %[vhi], %[uhi], %[vhi], %[mhi] bitop3:0xf4"
-            : [vlo] "+v"(vlo[q]), [vhi] "+v"(vhi[q]), [c] "+s"(carry), [ulo] "=&v"(t0),
+            : [vlo] "+v"(vlo[0]), [vhi] "+v"(vhi[0]), [c] "+s"(carry), [ulo] "=&v"(t0),
               [uhi] "=&v"(t1)
             : [mlo] "v"(mlo), [mhi] "v"(mhi));
+    } else {
+#pragma unroll
+        for (int q = 0; q < WPL; q += 2) {
+            const uint32_t mlo0 = (uint32_t)M[q], mhi0 = (uint32_t)(M[q] >> 32);
+            const uint32_t mlo1 = (uint32_t)M[q + 1], mhi1 = (uint32_t)(M[q + 1] >> 32);
+            uint32_t t0, t1;
+            asm("v_and_b32 %[ulo], %[vlo0], %[mlo0]\n\t"
+                "v_addc_co_u32 %[ulo], %[c], %[vlo0], %[ulo], %[c]\n\t"
+                "v_bitop3_b32 %[vlo0], %[ulo], %[vlo0], %[mlo0] bitop3:0xf4\n\t"
+                "v_and_b32 %[uhi], %[vhi0], %[mhi0]\n\t"
+                "v_addc_co_u32 %[uhi], %[c], %[vhi0], %[uhi], %[c]\n\t"
+                "v_bitop3_b32 %[vhi0], %[uhi], %[vhi0], %[mhi0] bitop3:0xf4\n\t"
+                "v_and_b32 %[ulo], %[vlo1], %[mlo1]\n\t"
+                "v_addc_co_u32 %[ulo], %[c], %[vlo1], %[ulo], %[c]\n\t"
+                "v_bitop3_b32 %[vlo1], %[ulo], %[vlo1], %[mlo1] bitop3:0xf4\n\t"
+                "v_and_b32 %[uhi], %[vhi1], %[mhi1]\n\t"
+                "v_addc_co_u32 %[uhi], %[c], %[vhi1], %[uhi], %[c]\n\t"
+                "v_bitop3_b32 %[vhi1], %[uhi], %[vhi1], %[mhi1] bitop3:0xf4"
+                : [vlo0] "+v"(vlo[q]), [vhi0] "+v"(vhi[q]), [vlo1] "+v"(vlo[q + 1]),
+                  [vhi1] "+v"(vhi[q + 1]), [c] "+s"(carry), [ulo] "=&v"(t0), [uhi] "=&v"(t1)
+                : [mlo0] "v"(mlo0), [mhi0] "v"(mhi0), [mlo1] "v"(mlo1), [mhi1] "v"(mhi1));
+        }
     }
 }
 

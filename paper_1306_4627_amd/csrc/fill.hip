@@ -17,8 +17,12 @@ namespace lcs {
 // fill
 // --------------------------------------------------------------------------
 
-size_t fill_lds_bytes(int wpl, int sigma) {
-    return (size_t)fill_waves(sigma, wpl) * (size_t)(sigma + 1) * (size_t)wpl * 64 * sizeof(uint64_t);
+size_t fill_lds_bytes(int wpl, int sigma, int mode) {
+    const size_t waves = (size_t)fill_waves(sigma, wpl);
+    // match masks: [symbol + sentinel][word][lane] per wave; the threshold
+    // pass adds 128 32-bit words per wave (segment sums and answers)
+    return waves * (size_t)(sigma + 1) * (size_t)wpl * 64 * sizeof(uint64_t) +
+           (mode == kFillThreshold ? waves * 128 * sizeof(uint32_t) : 0);
 }
 
 // Sixteen stream values (two per dword) starting at step t0.
@@ -34,15 +38,21 @@ __device__ __forceinline__ void load16(const uint16_t *ys, uint32_t t0, uint32_t
 
 // Sixteen column steps t..t+15 of one lane.  The carry-in lane mask of a
 // step is the carry-out mask of the previous step shifted up by one lane,
-// with segment starts cleared; with CHAIN, lane 0 takes the hand-over bit of
-// the feeding item (inbits, one bit per step) and lane 63's carry-out is
-// collected into outbits for the next item.  With TB, every lane's carry-in
-// bits are accumulated (newest in bit 0) and stored every 32 steps.
+// with segment starts cleared.  With CHAIN, lane 0 takes the hand-over bit
+// of the feeding item and lane 63's carry-out is collected for the next
+// item: one scalar add-with-carry chain shifts the mask (2 * mask, the carry
+// into the low word being the next step's hand-over bit, selected by
+// s_bitcmp1 from `innext`, bit s = the bit of step s+1) and lane 63's carry
+// (bit 63 of the mask) is shifted into `ow` (most recent step in bit 0): in
+// the traceback fill by the same chain's carry out, elsewhere by plain code
+// the compiler schedules (the forms that measured fastest for each).  With TB, every lane's carry-in bits are accumulated (newest in bit 0:
+// acc = 2 * acc + carry-in, one v_addc_co_u32 with the mask as carry-in) and
+// stored every 32 steps.
 template <int WPL, bool TB, bool CHAIN, bool RAW>
 __device__ __forceinline__ void run16(const uint32_t (&Yg)[8], uint32_t t, const char *lanecol,
                                       uint64_t notstart, uint64_t &cmask, uint32_t &acc,
                                       uint32_t *cbp, uint32_t (&vlo)[WPL], uint32_t (&vhi)[WPL],
-                                      uint64_t &inbits, uint64_t &outbits) {
+                                      uint32_t innext, uint32_t &ow) {
     constexpr int H = LCS_FILL_HOIST;   // steps whose match masks are read together
 #pragma unroll
     for (int h = 0; h < 16 / H; ++h) {
@@ -62,23 +72,35 @@ __device__ __forceinline__ void run16(const uint32_t (&Yg)[8], uint32_t t, const
 #pragma unroll
         for (int e = 0; e < H; ++e) {
             uint64_t cm = cmask;
-            if (CHAIN) {
-                cm |= inbits & 1ull;
-                inbits >>= 1;
-            }
             if (TB) {
-                uint32_t cj;
-                acc = __builtin_addc(acc, acc, (uint32_t)__builtin_amdgcn_inverse_ballot_w64(cm), &cj);
+                asm("v_addc_co_u32 %[a], vcc, %[a], %[a], %[m]" : [a] "+v"(acc) : [m] "s"(cm) : "vcc");
                 if (h * H + e == 15 && (t & 16u)) cbp[(size_t)((t + 15) >> 5) * 64] = acc;
             }
             column_step<WPL>(vlo, vhi, Mg[e], cm);
             if (CHAIN) {
-                outbits = (outbits >> 1) | (cm & 0x8000000000000000ull);
-                // pin the accumulation to this step: sunk to its single use,
-                // it would keep every step's carry mask alive until the chunk end
-                asm volatile("" : "+s"(outbits), "+s"(inbits));
+                const uint32_t clo = (uint32_t)cm, chi = (uint32_t)(cm >> 32);
+                uint32_t lo, hi;
+                if (TB) {
+                    asm("s_bitcmp1_b32 %[in], %[bit]\n\t"
+                        "s_addc_u32 %[lo], %[clo], %[clo]\n\t"
+                        "s_addc_u32 %[hi], %[chi], %[chi]\n\t"
+                        "s_addc_u32 %[ow], %[ow], %[ow]"
+                        : [lo] "=&s"(lo), [hi] "=&s"(hi), [ow] "+s"(ow)
+                        : [in] "s"(innext), [bit] "i"(h * H + e), [clo] "s"(clo), [chi] "s"(chi)
+                        : "scc");
+                } else {
+                    asm("s_bitcmp1_b32 %[in], %[bit]\n\t"
+                        "s_addc_u32 %[lo], %[clo], %[clo]\n\t"
+                        "s_addc_u32 %[hi], %[chi], %[chi]"
+                        : [lo] "=&s"(lo), [hi] "=&s"(hi)
+                        : [in] "s"(innext), [bit] "i"(h * H + e), [clo] "s"(clo), [chi] "s"(chi)
+                        : "scc");
+                    ow = (ow << 1) | (chi >> 31);
+                }
+                cmask = (((uint64_t)hi << 32) | lo) & notstart;
+            } else {
+                cmask = (cm << 1) & notstart;
             }
-            cmask = (cm << 1) & notstart;
         }
         // keep the scheduler from spreading the scalar work of many steps
         // across each other (it would hold dozens of masks live)
@@ -86,11 +108,62 @@ __device__ __forceinline__ void run16(const uint32_t (&Yg)[8], uint32_t t, const
     }
 }
 
+// Zero bits among this lane's valid rows of V: the lane's share of
+// c[m][j] for the column it holds (rows above m are padding).
+template <int WPL>
+__device__ __forceinline__ uint32_t lane_zeros(const uint32_t (&vlo)[WPL], const uint32_t (&vhi)[WPL],
+                                               int32_t pair, uint32_t word0, uint32_t m) {
+    uint32_t zeros = 0;
+    if (pair >= 0) {
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) {
+            const uint32_t row0 = (word0 + q) * 64u;
+            if (row0 < m) {
+                const uint32_t cnt = (m - row0) < 64u ? (m - row0) : 64u;
+                const uint64_t mask = cnt == 64u ? ~0ull : ((1ull << cnt) - 1);
+                const uint64_t v = ((uint64_t)vhi[q] << 32) | vlo[q];
+                zeros += cnt - (uint32_t)__builtin_popcountll(v & mask);
+            }
+        }
+    }
+    return zeros;
+}
+
+// Answer word of a pair (relaxed, device scope: other waves set it).  Idle
+// lanes read pair 0's word and report 0; no branch, so the load can sit
+// between column steps without splitting the wave's control flow.
+__device__ __forceinline__ uint32_t load_state(uint32_t *dec, int32_t pair) {
+    const uint32_t d = __hip_atomic_load(dec + (pair >= 0 ? pair : 0), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return pair >= 0 ? d : 0u;
+}
+
+__device__ __forceinline__ uint32_t clamp_col(int64_t j, uint32_t n) {
+    return j <= 0 ? 0u : (j >= (int64_t)n ? n : (uint32_t)j);
+}
+
 // Y stream element: code * (WPL * 512), i.e. the byte offset of the code's
 // row of match masks in the wave's LDS block ([symbol][word][lane] layout);
 // with RAW the plain code, shifted here.
-template <int WPL, bool TB, bool RAW>
+//
+// MODE kFillThreshold (section II's yes/no question: does the child keep at
+// least a given share of the parent?): at the start of every chunk each lane
+// counts the zero bits of its rows, the counts are summed per pair segment of
+// the wave, and a chained item adds the running sum handed up by the item
+// below (taken at the start of that item's previous chunk) and hands the new
+// sum up with its carries.  The one-chunk delay per item offsets the item's
+// 64 extra steps of skew, so the sum H seen by a pair's top lane covers every
+// row block at columns falling by one per lane from Jb (bottom lane) to J
+// (top lane).  Column steps raise c by at most one, hence
+// H - (Jb - J) <= c[m][J] <= H, and since c[m][n] >= c[m][J] and
+// c[m][n] <= c[m][J] + (n - J), the pair reaches its target T once
+// H - (Jb - J) >= T and cannot once H + (n - J) < T.  The top lane then
+// records the answer; a wave whose pairs are all answered stops, and so do
+// the items of a chain once its pair is.
+template <int WPL, int MODE, bool RAW>
 __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
+    constexpr bool TB = MODE == kFillTraceback;
+    constexpr bool THR = MODE == kFillThreshold;
     extern __shared__ uint64_t smem[];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -99,6 +172,9 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
     uint64_t *pm = smem + (size_t)wv * sig1 * RS;
     // this lane's column of the wave's block; a stream value is a byte offset
     const char *lanecol = (const char *)(pm + lane);
+    // threshold pass: 64 segment sums and 64 segment answers per wave
+    uint32_t *tslot = nullptr;
+    if (THR) tslot = (uint32_t *)(smem + (size_t)(blockDim.x >> 6) * sig1 * RS) + wv * 128;
 
     for (;;) {
         uint32_t ticket = 0;
@@ -169,7 +245,29 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
         // the buffer is zeroed before every pass.
         uint64_t *xf_out = feeds ? a.xfer + a.it_xf[item] : nullptr;
         uint64_t *xf_in = prev >= 0 ? a.xfer + a.it_xf[prev] : nullptr;
-        bool aborted = false;
+        // threshold pass: the running sums travel the same way, one tagged
+        // word per chunk
+        uint64_t *xs_out = (THR && feeds) ? a.xsum + a.it_xf[item] / 2 : nullptr;
+        const uint64_t *xs_in = (THR && prev >= 0) ? a.xsum + a.it_xf[prev] / 2 : nullptr;
+        // threshold pass: this lane's segment (first lane, top lane) and the
+        // state of its pair; `live_in` drops once the chained pair entering
+        // at lane 0 is answered (nothing more needs to come from below)
+        int seg0 = 0;
+        bool seg_top = false;
+        uint32_t nq = 0, tq = 0, pdec = 0, pdec_nx = 0;
+        bool live_in = prev >= 0;
+        if (THR) {
+            const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+            seg0 = 63 - __builtin_clzll((startmask | 1ull) & upto);
+            const int32_t pair_up = __shfl(pair, lane == 63 ? 63 : lane + 1);
+            seg_top = pair >= 0 && (lane == 63 || pair_up != pair);
+            if (pair >= 0) {
+                nq = a.pair_n[pair];
+                tq = a.thr_t[pair];
+            }
+            pdec = load_state(a.thr_dec, pair);
+        }
+        bool aborted = false, stopped = false;
         // Stream values, two per dword, in a ring of four 16-step groups; the
         // group 32 steps ahead is requested before the current one is used,
         // so the stream's memory latency hides behind two groups of work.
@@ -181,113 +279,184 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
         // their instructions first; shorter items fill the remaining slots.
         if (T >= a.prio_T) __builtin_amdgcn_s_setprio(2);
         else __builtin_amdgcn_s_setprio(0);
-        uint64_t pw0 = 0, pw1 = 0;   // hand-over words requested one group early
+        uint64_t pw0 = 0, pw1 = 0, pw2 = 0;   // hand-over words requested one group early
 
         for (uint32_t c = 0; c < nch; ++c) {
-            uint64_t inbits = 0, outbits = 0;
-            if (prev >= 0 && c > 0) {
-                uint64_t w0 = uniform64(pw0), w1 = uniform64(pw1);
+            uint64_t inbits = 0;
+            uint32_t hin = 0;
+            if (live_in && c > 0) {
+                uint64_t w0 = uniform64(pw0), w1 = uniform64(pw1), w2 = THR ? uniform64(pw2) : 0;
                 uint32_t spins = 0;
-                while ((uint32_t)(w0 >> 32) != c || (uint32_t)(w1 >> 32) != c) {
+                while ((uint32_t)(w0 >> 32) != c || (uint32_t)(w1 >> 32) != c ||
+                       (THR && (uint32_t)(w2 >> 32) != c)) {
                     // bounded wait for the feeding item to finish chunk c-1
                     if (++spins > a.spin_limit) { aborted = true; break; }
+                    if (THR) {
+                        // the pair may have been answered, and the feeder gone
+                        const uint32_t d = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                            a.thr_dec + __builtin_amdgcn_readfirstlane(pair), __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT));
+                        if (d) { stopped = true; break; }
+                    }
                     __builtin_amdgcn_s_sleep(1);
                     w0 = uniform64(__hip_atomic_load(xf_in + 2 * (c - 1), __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT));
                     w1 = uniform64(__hip_atomic_load(xf_in + 2 * (c - 1) + 1, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT));
+                    if (THR)
+                        w2 = uniform64(__hip_atomic_load(xs_in + (c - 1), __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT));
                 }
-                if (aborted) break;
+                if (aborted || stopped) break;
                 inbits = (w1 << 32) | (w0 & 0xffffffffull);
+                hin = (uint32_t)w2;
+                cmask |= inbits & 1ull;   // lane 0's carry-in of the chunk's first step
+            }
+            const uint32_t t = c * 64u;
+            uint32_t hout = 0;
+            if (THR) {
+                if (!pdec) pdec = pdec_nx;
+                if (c > 0) {
+                    // segment sums of the zero counts (LDS, in wave order)
+                    const uint32_t z = lane_zeros<WPL>(vlo, vhi, pair, word0, m);
+                    tslot[lane] = 0;
+                    tslot[64 + lane] = 0;
+                    wave_lds_sync();
+                    atomicAdd(tslot + seg0, z);
+                    wave_lds_sync();
+                    uint32_t h = tslot[seg0];
+                    if (seg0 == 0 && prev >= 0) h += hin;
+                    hout = __builtin_amdgcn_readlane(h, 63);
+                    if (seg_top && pdec == 0 && !(lane == 63 && feeds)) {
+                        // this lane tops its pair: columns J (own) and Jb
+                        // (bottom lane, h items and as many chunks below)
+                        const uint32_t J = clamp_col((int64_t)t - (int64_t)skew, nq);
+                        const uint32_t below = skew / (uint32_t)(kLanes - 1 + kChunk);
+                        const uint32_t Jb = clamp_col(64 * ((int64_t)c - (int64_t)below), nq);
+                        uint32_t d = 0;
+                        if ((uint64_t)h >= (uint64_t)tq + (Jb - J)) d = 1;
+                        else if ((uint64_t)h + (nq - J) < (uint64_t)tq) d = 2;
+                        if (d) {
+                            __hip_atomic_store(a.thr_dec + pair, d, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            tslot[64 + seg0] = d;
+                        }
+                    }
+                    wave_lds_sync();
+                    const uint32_t dl = tslot[64 + seg0];
+                    if (dl && pair >= 0) pdec = dl;
+                }
+                // every pair of the wave answered: stop
+                if (__builtin_amdgcn_ballot_w64(pair >= 0 && pdec == 0) == 0) {
+                    stopped = true;
+                    break;
+                }
+                // the chained pair at lane 0 answered: stop waiting for it
+                if (live_in && __builtin_amdgcn_readlane(pdec, 0) != 0) live_in = false;
             }
             if (TB && ((c * 64u) % (uint32_t)a.ckpt_every) == 0) {
                 uint64_t *dst = ckp + (size_t)((c * 64u) / (uint32_t)a.ckpt_every) * RS;
 #pragma unroll
                 for (int q = 0; q < WPL; ++q) dst[q * 64] = ((uint64_t)vhi[q] << 32) | vlo[q];
             }
-            const uint32_t t = c * 64u;
             if (chain) {
+                // hand-over bits of the next step: bit s of each group's word
+                // is the bit of step (group start + s + 1) of the chunk
+                uint32_t ow_lo = 0, ow_hi = 0;
                 load16(ys, t + 32, Y2);
-                run16<WPL, TB, true, RAW>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                run16<WPL, TB, true, RAW>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
+                                          (uint32_t)(inbits >> 1), ow_lo);
                 load16(ys, t + 48, Y3);
-                run16<WPL, TB, true, RAW>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                run16<WPL, TB, true, RAW>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
+                                          (uint32_t)(inbits >> 17), ow_lo);
                 load16(ys, t + 64, Y0);
-                run16<WPL, TB, true, RAW>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                run16<WPL, TB, true, RAW>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
+                                          (uint32_t)(inbits >> 33), ow_hi);
                 load16(ys, t + 80, Y1);
-                if (prev >= 0) {
+                if (live_in) {
                     pw0 = __hip_atomic_load(xf_in + 2 * c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     pw1 = __hip_atomic_load(xf_in + 2 * c + 1, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
+                    if (THR)
+                        pw2 = __hip_atomic_load(xs_in + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                run16<WPL, TB, true, RAW>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                if (THR) pdec_nx = load_state(a.thr_dec, pair);
+                run16<WPL, TB, true, RAW>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
+                                          (uint32_t)(inbits >> 49), ow_hi);
+                // lane 63's carries of the chunk, step e in bit e
+                const uint64_t outbits =
+                    ((uint64_t)__builtin_bitreverse32(ow_hi) << 32) | __builtin_bitreverse32(ow_lo);
                 if (feeds && lane == 0) {
                     const uint64_t tag = (uint64_t)(c + 1) << 32;
                     __hip_atomic_store(xf_out + 2 * c, tag | (outbits & 0xffffffffull),
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     __hip_atomic_store(xf_out + 2 * c + 1, tag | (outbits >> 32), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
+                    if (THR)
+                        __hip_atomic_store(xs_out + c, tag | hout, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
                 }
             } else {
+                uint32_t dummy_ow = 0;
                 load16(ys, t + 32, Y2);
-                run16<WPL, TB, false, RAW>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                run16<WPL, TB, false, RAW>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
                 load16(ys, t + 48, Y3);
-                run16<WPL, TB, false, RAW>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                run16<WPL, TB, false, RAW>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
                 load16(ys, t + 64, Y0);
-                run16<WPL, TB, false, RAW>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                run16<WPL, TB, false, RAW>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
                 load16(ys, t + 80, Y1);
-                run16<WPL, TB, false, RAW>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, inbits, outbits);
+                if (THR) pdec_nx = load_state(a.thr_dec, pair);
+                run16<WPL, TB, false, RAW>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
             }
         }
         if (aborted) {
             if (lane == 0) atomicOr(a.error, 1u);
             return;
         }
+        // an answered pair's length is not needed (and not complete)
+        if (THR && stopped) continue;
 
         // ---- length: zero bits among the valid rows ----
-        if (pair >= 0) {
-            uint32_t zeros = 0;
-#pragma unroll
-            for (int q = 0; q < WPL; ++q) {
-                const uint32_t row0 = (word0 + q) * 64u;
-                if (row0 < m) {
-                    const uint32_t cnt = (m - row0) < 64u ? (m - row0) : 64u;
-                    const uint64_t mask = cnt == 64u ? ~0ull : ((1ull << cnt) - 1);
-                    const uint64_t v = ((uint64_t)vhi[q] << 32) | vlo[q];
-                    zeros += cnt - (uint32_t)__builtin_popcountll(v & mask);
-                }
-            }
-            if (zeros) atomicAdd((unsigned long long *)(a.out_len + pair), (unsigned long long)zeros);
-        }
+        const uint32_t zeros = lane_zeros<WPL>(vlo, vhi, pair, word0, m);
+        if (zeros) atomicAdd((unsigned long long *)(a.out_len + pair), (unsigned long long)zeros);
     }
 }
 
-const void *fill_symbol(int wpl, bool tb, bool raw) {
-    if (raw) {
-        if (wpl == 1) return tb ? (const void *)&k_fill<1, true, true> : (const void *)&k_fill<1, false, true>;
-        return tb ? (const void *)&k_fill<2, true, true> : (const void *)&k_fill<2, false, true>;
+const void *fill_symbol(int wpl, int mode, bool raw) {
+#define LCS_FILL_SYM(W, R)                                                   \
+    if (wpl == W && raw == R) {                                              \
+        if (mode == kFillTraceback) return (const void *)&k_fill<W, kFillTraceback, R>; \
+        if (mode == kFillThreshold) return (const void *)&k_fill<W, kFillThreshold, R>; \
+        return (const void *)&k_fill<W, kFillLength, R>;                     \
     }
-    switch (wpl) {
-        case 1: return tb ? (const void *)&k_fill<1, true, false> : (const void *)&k_fill<1, false, false>;
-        case 2: return tb ? (const void *)&k_fill<2, true, false> : (const void *)&k_fill<2, false, false>;
-        case 4: return tb ? (const void *)&k_fill<4, true, false> : (const void *)&k_fill<4, false, false>;
-        default: return tb ? (const void *)&k_fill<8, true, false> : (const void *)&k_fill<8, false, false>;
-    }
+    LCS_FILL_SYM(1, false)
+    LCS_FILL_SYM(2, false)
+    LCS_FILL_SYM(4, false)
+    LCS_FILL_SYM(8, false)
+    LCS_FILL_SYM(1, true)
+    LCS_FILL_SYM(2, true)
+#undef LCS_FILL_SYM
+    return nullptr;
 }
 
 int fill_block(int wpl, int sigma) { return 64 * fill_waves(sigma, wpl); }
 
-hipError_t launch_fill(int wpl, bool tb, const FillArgs &a, uint32_t grid, hipStream_t s) {
+hipError_t launch_fill(int wpl, int mode, const FillArgs &a, uint32_t grid, hipStream_t s) {
     if (!wpl_fits(a.sigma, wpl)) return hipErrorInvalidValue;
-    const size_t lds = fill_lds_bytes(wpl, a.sigma);
+    if (mode == kFillThreshold && (!a.pair_n || !a.thr_t || !a.thr_dec || !a.xsum))
+        return hipErrorInvalidValue;
+    const size_t lds = fill_lds_bytes(wpl, a.sigma, mode);
     const dim3 block((uint32_t)fill_block(wpl, a.sigma));
     const bool raw = raw_stream(a.sigma, wpl);
-#define LCS_FILL_CASE(W, R)                                                            \
-    if (wpl == W && raw == R) {                                                        \
-        if (tb)                                                                        \
-            hipLaunchKernelGGL((k_fill<W, true, R>), dim3(grid), block, lds, s, a);    \
-        else                                                                           \
-            hipLaunchKernelGGL((k_fill<W, false, R>), dim3(grid), block, lds, s, a);   \
-        return hipGetLastError();                                                      \
+#define LCS_FILL_CASE(W, R)                                                                  \
+    if (wpl == W && raw == R) {                                                              \
+        if (mode == kFillTraceback)                                                          \
+            hipLaunchKernelGGL((k_fill<W, kFillTraceback, R>), dim3(grid), block, lds, s, a); \
+        else if (mode == kFillThreshold)                                                     \
+            hipLaunchKernelGGL((k_fill<W, kFillThreshold, R>), dim3(grid), block, lds, s, a); \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_fill<W, kFillLength, R>), dim3(grid), block, lds, s, a);   \
+        return hipGetLastError();                                                            \
     }
     LCS_FILL_CASE(1, false)
     LCS_FILL_CASE(2, false)

@@ -28,6 +28,13 @@ struct PrepArgs {
     uint64_t nzero;
     uint64_t *zero64;          // traceback bitmaps zeroed here
     uint64_t nzero64;
+    // threshold pass (null otherwise): the state word of each pair is set
+    // here from its target: 1 for a target of 0, 2 for one above min(m, n)
+    // (both settled before any column), else 0
+    const uint32_t *pair_m;
+    const uint32_t *pair_n;
+    const uint32_t *thr_t;
+    uint32_t *thr_dec;
 };
 
 // Fill: one class (fixed words per lane), persistent waves.
@@ -58,7 +65,18 @@ struct FillArgs {
     uint32_t spin_limit;       // polls before a wait gives up
     int32_t sigma;             // code sigma is the zero-mask sentinel
     int32_t ckpt_every;        // steps between checkpoints (traceback only)
+    // threshold pass only
+    const uint32_t *pair_n;    // columns of each pair
+    const uint32_t *thr_t;     // target length of each pair
+    uint32_t *thr_dec;         // 0 open, 1 reaches its target, 2 cannot
+    uint64_t *xsum;            // running zero counts handed up a chain: one
+                               // tagged word per chunk per feeder (zeroed)
 };
+
+// What a fill launch computes: lengths only, lengths plus the checkpoints the
+// traceback reads, or the threshold pass (lengths of the pairs it does not
+// settle early).
+enum FillMode { kFillLength = 0, kFillTraceback = 1, kFillThreshold = 2 };
 
 // Traceback walk: one wave per ticket, persistent.  The walk records the
 // rows where it takes a diagonal step in a per-pair bitmap over X (bit r of
@@ -125,15 +143,15 @@ struct EmitArgs {
 constexpr int kFillBlock = 256;   // at most four independent waves per work-group
 constexpr int kTbBlock = 256;
 
-size_t fill_lds_bytes(int wpl, int sigma);
+size_t fill_lds_bytes(int wpl, int sigma, int mode);
 size_t tb_lds_bytes(int wpl, int sigma, int ckpt_every, int nb, int bands);
 
-const void *fill_symbol(int wpl, bool tb, bool raw);
+const void *fill_symbol(int wpl, int mode, bool raw);
 int fill_block(int wpl, int sigma);   // threads per fill work-group
 const void *tb_symbol(int wpl, int ckpt_every);
 
 hipError_t launch_prep(const PrepArgs &a, uint64_t xbytes_n, hipStream_t s);
-hipError_t launch_fill(int wpl, bool traceback, const FillArgs &a, uint32_t grid, hipStream_t s);
+hipError_t launch_fill(int wpl, int mode, const FillArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_tb(int wpl, const TbArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_emit(const EmitArgs &a, hipStream_t s);
 

@@ -69,6 +69,7 @@ struct ClassDev {
     uint64_t *ckpt = nullptr;
     uint32_t *cbits = nullptr;
     uint64_t *xfer = nullptr;
+    uint64_t *xsum = nullptr;          // threshold pass: running sums handed up chains
     uint32_t *plain_ctr = nullptr;     // plain mode: kQueues queue counters per pair
     uint32_t *q_fill = nullptr, *q_spec = nullptr, *q_fix = nullptr, *q_seal = nullptr;
     uint32_t fill_grid = 1, sp_grid = 1, fx_grid = 1, sl_grid = 1;
@@ -139,6 +140,12 @@ struct lcs_batch {
     uint64_t *zero64 = nullptr;
     uint64_t nzero64 = 0;
     uint32_t *error = nullptr;
+    // threshold pass: per-pair target length (host copy and device) and
+    // answer word (0 open, 1 reaches the target, 2 cannot; read back with the
+    // lengths)
+    uint32_t *thr_t = nullptr, *thr_dec = nullptr;
+    std::vector<uint32_t> thr_host;
+    bool thr_set = false;
     std::vector<ClassDev> cls;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -156,6 +163,11 @@ static thread_local char g_last_error[256] = "";
 static void note_error(const char *what, hipError_t e) {
     std::snprintf(g_last_error, sizeof g_last_error, "%s: %s (%d)", what, hipGetErrorString(e),
                   (int)e);
+}
+
+static int fill_mode(uint32_t flags) {
+    return (flags & LCS_WANT_TRACEBACK) ? kFillTraceback
+                                        : (flags & LCS_THRESHOLD) ? kFillThreshold : kFillLength;
 }
 
 static lcs_status dev_err(hipError_t e) {
@@ -379,6 +391,8 @@ static size_t carve(lcs_batch *b, char *base) {
     b->em_w0 = cv.take<uint32_t>(b->em_w0_host.size() + 1);
     b->pair_m = cv.take<uint32_t>(np + 1);
     b->pair_n = cv.take<uint32_t>(np + 1);
+    const bool thr = (b->flags & LCS_THRESHOLD) != 0;
+    b->thr_t = thr ? cv.take<uint32_t>(np + 1) : nullptr;
     const size_t ns = p.segs.size();
     b->seg_yoff = cv.take<uint64_t>(ns + 1);
     b->seg_begin = cv.take<uint64_t>(ns + 1);
@@ -422,6 +436,7 @@ static size_t carve(lcs_batch *b, char *base) {
     b->upload_bytes = cv.off;
     // ---- read back after a pass (one copy of [out_len, end of out)) ----
     b->out_len = cv.take<uint64_t>(np + 1);
+    b->thr_dec = thr ? cv.take<uint32_t>(np + 1) : nullptr;
     // zeroed before every pass, 32-bit: error word, then per class the fill
     // and traceback queue counters and (plain mode) kQueues counters per pair
     uint64_t nz = 1;
@@ -441,7 +456,7 @@ static size_t carve(lcs_batch *b, char *base) {
     // zeroed before every pass, 64-bit: traceback bitmaps, then the carry
     // hand-over words of every class
     uint64_t nz64 = (b->flags & LCS_WANT_TRACEBACK) ? b->diag_words : 0;
-    for (const ClassPlan &C : p.classes) nz64 += C.xf_words;
+    for (const ClassPlan &C : p.classes) nz64 += C.xf_words + (thr ? C.xf_words / 2 : 0);
     b->zero64 = cv.take<uint64_t>(nz64 + 1);
     b->nzero64 = nz64;
     b->diag = b->zero64;
@@ -456,6 +471,10 @@ static size_t carve(lcs_batch *b, char *base) {
         D.cbits = cv.take<uint32_t>(C.cb_words + 1);
         D.xfer = b->zero64 ? b->zero64 + z64 : nullptr;
         z64 += C.xf_words;
+        if (thr) {
+            D.xsum = b->zero64 ? b->zero64 + z64 : nullptr;
+            z64 += C.xf_words / 2;
+        }
         D.q_fill = b->zero ? b->zero + zc : nullptr;
         D.q_spec = b->zero ? b->zero + zc + 1 : nullptr;
         D.q_fix = b->zero ? b->zero + zc + 2 : nullptr;
@@ -494,7 +513,8 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
                               const lcs_tuning *tuning, lcs_batch **out,
                               const BatchHooks *hooks = nullptr) {
     if (!ctx || !out) return LCS_ERR_ARG;
-    if (flags & ~(uint32_t)(LCS_WANT_TRACEBACK | LCS_USE_GRAPH)) return LCS_ERR_ARG;
+    if (flags & ~(uint32_t)(LCS_WANT_TRACEBACK | LCS_USE_GRAPH | LCS_THRESHOLD)) return LCS_ERR_ARG;
+    if ((flags & LCS_THRESHOLD) && (flags & LCS_WANT_TRACEBACK)) return LCS_ERR_ARG;
     lcs_status st = check_pairs(pairs, count);
     if (st) return st;
     st = check_tuning(tuning);
@@ -676,8 +696,9 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         {
             const int fw = fill_block(C.wpl, sigma) / 64;   // waves per fill work-group
             D.fill_waves = fw;
-            D.fill_grid = resident_grid(ctx, fill_symbol(C.wpl, cfg.traceback, raw_stream(sigma, C.wpl)),
-                                        fill_lds_bytes(C.wpl, sigma), (D.nitems + fw - 1) / fw,
+            const int mode = fill_mode(flags);
+            D.fill_grid = resident_grid(ctx, fill_symbol(C.wpl, mode, raw_stream(sigma, C.wpl)),
+                                        fill_lds_bytes(C.wpl, sigma, mode), (D.nitems + fw - 1) / fw,
                                         cap > 0 ? (cap + fw - 1) / fw : 0, 64 * fw);
         }
         // raised priority for the items within half of the longest
@@ -777,10 +798,17 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
     pa.nzero = b->nzero;
     pa.zero64 = b->zero64;
     pa.nzero64 = b->nzero64;
+    if (b->flags & LCS_THRESHOLD) {
+        pa.pair_m = b->pair_m;
+        pa.pair_n = b->pair_n;
+        pa.thr_t = b->thr_t;
+        pa.thr_dec = b->thr_dec;
+    }
     if (events) HIP_TRY(hipEventRecord(b->ev[0], s));
     HIP_TRY(launch_prep(pa, b->xarena + 64, s));
     if (events) HIP_TRY(hipEventRecord(b->ev[1], s));
     const bool tb = (b->flags & LCS_WANT_TRACEBACK) != 0;
+    const int mode = fill_mode(b->flags);
     auto fill_args = [&](size_t ci) {
         const ClassDev &D = b->cls[ci];
         FillArgs fa{};
@@ -810,6 +838,12 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         fa.spin_limit = b->spin_limit;
         fa.sigma = b->sigma;
         fa.ckpt_every = b->ckpt;
+        if (mode == kFillThreshold) {
+            fa.pair_n = b->pair_n;
+            fa.thr_t = b->thr_t;
+            fa.thr_dec = b->thr_dec;
+            fa.xsum = D.xsum;
+        }
         return fa;
     };
     auto tb_args = [&](size_t ci, int32_t mode) {
@@ -879,7 +913,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         for (size_t ci = 0; ci < b->cls.size(); ++ci) {
             const ClassDev &D = b->cls[ci];
             if (!D.nitems) continue;
-            HIP_TRY(launch_fill(D.wpl, tb, fill_args(ci), D.fill_grid, s));
+            HIP_TRY(launch_fill(D.wpl, mode, fill_args(ci), D.fill_grid, s));
         }
         if (events) HIP_TRY(hipEventRecord(b->ev[2], s));
         if (tb) {
@@ -904,7 +938,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
                 fa.item_end = D.pl_end[k];
                 fa.queue = ctr + kQueues * k;
                 uint32_t g = (fa.item_end - fa.item_begin + D.fill_waves - 1) / D.fill_waves;
-                HIP_TRY(launch_fill(D.wpl, tb, fa, g, s));
+                HIP_TRY(launch_fill(D.wpl, mode, fa, g, s));
                 if (tb) {
                     TbArgs ta = tb_args(ci, kTbSpec);
                     ta.tk_t += D.pl_sp[k];
@@ -948,6 +982,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
 // it; the others enqueue the kernels directly.
 static lcs_status launch_pass(lcs_batch *b, bool eager) {
     lcs_ctx *ctx = b->ctx;
+    if ((b->flags & LCS_THRESHOLD) && !b->thr_set) return LCS_ERR_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
     hipStream_t s = b->hooks.stream ? b->hooks.stream : ctx->stream;
     if ((b->flags & LCS_USE_GRAPH) && !b->plain && !eager) {
@@ -1022,13 +1057,81 @@ static lcs_status readback(lcs_batch *b, bool strings, std::vector<uint8_t> &hos
     return LCS_OK;
 }
 
+// Threshold pass: answers and lengths from a read-back image (a pair
+// answered before its last column has no length).
+static lcs_status threshold_results(const lcs_batch *b, const std::vector<uint8_t> &host,
+                                    uint8_t *out_pass, uint64_t *out_len) {
+    const uint64_t *L = (const uint64_t *)host.data();
+    const uint32_t *dec = (const uint32_t *)(host.data() + ((char *)b->thr_dec - (char *)b->out_len));
+    for (uint64_t k = 0; k < b->npairs; ++k) {
+        uint64_t len = LCS_LENGTH_UNKNOWN;
+        uint8_t pass = 0;
+        if (dec[k] == 1u || dec[k] == 2u) {
+            pass = dec[k] == 1u;
+        } else if (dec[k] == 0u) {
+            if (L[k] > std::min(b->m[k], b->n[k])) return LCS_ERR_DEVICE;
+            len = L[k];
+            pass = L[k] >= b->thr_host[k];
+        } else {
+            return LCS_ERR_DEVICE;
+        }
+        if (out_pass) out_pass[k] = pass;
+        if (out_len) out_len[k] = len;
+    }
+    return LCS_OK;
+}
+
 extern "C" lcs_status lcs_batch_lengths(lcs_batch *b, uint64_t *out_lens) {
     if (!b || (b->npairs && !out_lens)) return LCS_ERR_ARG;
     std::vector<uint8_t> host;
     lcs_status st = readback(b, false, host);
     if (st) return st;
+    if (b->flags & LCS_THRESHOLD) return threshold_results(b, host, nullptr, out_lens);
     if (b->npairs) std::memcpy(out_lens, host.data(), b->npairs * 8);
     return LCS_OK;
+}
+
+// Least L in [0, m] whose similarity (100 * L) / m reaches pct (which is at
+// most 100, and (100 * m) / m is exactly 100); the similarity is
+// non-decreasing in L, so a binary search finds it.
+static uint32_t target_length(uint64_t m, double pct) {
+    if (m == 0) return 0;
+    auto sim = [&](uint64_t L) { return (100.0 * (double)L) / (double)m; };
+    if (sim(0) >= pct) return 0;
+    uint64_t lo = 0, hi = m;   // sim(lo) < pct <= sim(hi)
+    while (hi - lo > 1) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (sim(mid) >= pct) hi = mid;
+        else lo = mid;
+    }
+    return (uint32_t)hi;
+}
+
+extern "C" lcs_status lcs_batch_set_threshold(lcs_batch *b, double min_percent) {
+    if (!b || !(b->flags & LCS_THRESHOLD)) return LCS_ERR_ARG;
+    if (!(min_percent >= 0.0 && min_percent <= 100.0)) return LCS_ERR_ARG;
+    lcs_ctx *ctx = b->ctx;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
+    hipStream_t s = b->hooks.stream ? b->hooks.stream : ctx->stream;
+    // earlier passes may still read the old targets
+    HIP_TRY(hipStreamSynchronize(s));
+    b->thr_host.assign(b->npairs + 1, 0);
+    for (uint64_t k = 0; k < b->npairs; ++k) b->thr_host[k] = target_length(b->m[k], min_percent);
+    if (b->npairs) {
+        HIP_TRY(hipMemcpyAsync(b->thr_t, b->thr_host.data(), b->npairs * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    b->thr_set = true;
+    return LCS_OK;
+}
+
+extern "C" lcs_status lcs_batch_decisions(lcs_batch *b, uint8_t *out_pass, uint64_t *out_len) {
+    if (!b || !(b->flags & LCS_THRESHOLD)) return LCS_ERR_ARG;
+    if (b->npairs && !out_pass) return LCS_ERR_ARG;
+    std::vector<uint8_t> host;
+    lcs_status st = readback(b, false, host);
+    if (st) return st;
+    return threshold_results(b, host, out_pass, out_len);
 }
 
 extern "C" lcs_status lcs_batch_tracebacks(lcs_batch *b, uint8_t *out_arena, uint64_t arena_cap,
@@ -1135,6 +1238,32 @@ extern "C" lcs_status lcs_length_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint
     if (st) return st;
     st = lcs_batch_run(b);
     if (!st) st = lcs_batch_lengths(b, out_lens);
+    free_batch(b);
+    return st;
+}
+
+extern "C" lcs_status lcs_similarity_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                                           const lcs_alphabet *alphabet, double *out_percent) {
+    if (!ctx || (count && !out_percent)) return LCS_ERR_ARG;
+    std::vector<uint64_t> L(count + 1, 0);
+    lcs_status st = lcs_length_batch(ctx, pairs, count, alphabet, L.data());
+    if (st) return st;
+    for (uint64_t k = 0; k < count; ++k)
+        out_percent[k] = pairs[k].m ? (100.0 * (double)L[k]) / (double)pairs[k].m : 100.0;
+    return LCS_OK;
+}
+
+extern "C" lcs_status lcs_threshold_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                                          const lcs_alphabet *alphabet, double min_percent,
+                                          uint8_t *out_pass, uint64_t *out_len) {
+    if (!ctx || (count && !out_pass)) return LCS_ERR_ARG;
+    if (!(min_percent >= 0.0 && min_percent <= 100.0)) return LCS_ERR_ARG;
+    lcs_batch *b = nullptr;
+    lcs_status st = build_batch(ctx, pairs, count, alphabet, LCS_THRESHOLD, nullptr, &b);
+    if (st) return st;
+    st = lcs_batch_set_threshold(b, min_percent);
+    if (!st) st = lcs_batch_run(b);
+    if (!st) st = lcs_batch_decisions(b, out_pass, out_len);
     free_batch(b);
     return st;
 }
@@ -1370,7 +1499,8 @@ static lcs_status plan_only(const uint64_t *m, const uint64_t *n, uint64_t count
                             std::vector<PairShape> &shapes, Plan &plan) {
     if (count && (!m || !n)) return LCS_ERR_ARG;
     if (alphabet_size < 1 || alphabet_size > 256) return LCS_ERR_ARG;
-    if (flags & ~(uint32_t)(LCS_WANT_TRACEBACK | LCS_USE_GRAPH)) return LCS_ERR_ARG;
+    if (flags & ~(uint32_t)(LCS_WANT_TRACEBACK | LCS_USE_GRAPH | LCS_THRESHOLD)) return LCS_ERR_ARG;
+    if ((flags & LCS_THRESHOLD) && (flags & LCS_WANT_TRACEBACK)) return LCS_ERR_ARG;
     lcs_status st = check_tuning(tuning);
     if (st) return st;
     if (max_wpl(alphabet_size) == 0) return LCS_ERR_UNSUPPORTED;

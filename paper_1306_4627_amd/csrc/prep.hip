@@ -1,5 +1,6 @@
 // prep.hip -- per-pass input preparation: symbol remap of X, the zeroed
-// scratch words, and the per-segment Y streams read by the fill.
+// scratch words (and the starting state of a threshold pass), and the
+// per-segment Y streams read by the fill.
 #include "kernels.hpp"
 
 namespace lcs {
@@ -79,6 +80,13 @@ __global__ void k_zero(PrepArgs a) {
     for (uint64_t k = tid; k < a.npairs; k += stride) a.out_len[k] = 0;
     for (uint64_t k = tid; k < a.nzero; k += stride) a.zero_words[k] = 0;
     for (uint64_t k = tid; k < a.nzero64; k += stride) a.zero64[k] = 0;
+    // threshold pass: a target of 0 is reached before any column, and no
+    // pair can reach one above min(m, n) (the length never exceeds either)
+    if (a.thr_dec)
+        for (uint64_t k = tid; k < a.npairs; k += stride) {
+            const uint32_t T = a.thr_t[k], m = a.pair_m[k], n = a.pair_n[k];
+            a.thr_dec[k] = T == 0 ? 1u : (T > (m < n ? m : n) ? 2u : 0u);
+        }
 }
 
 hipError_t launch_prep(const PrepArgs &a, uint64_t xbytes_n, hipStream_t s) {

@@ -29,6 +29,8 @@ LCS_ERR_UNSUPPORTED = -7
 
 LCS_WANT_TRACEBACK = 1
 LCS_USE_GRAPH = 2
+LCS_THRESHOLD = 4
+LCS_LENGTH_UNKNOWN = (1 << 64) - 1
 
 DNA = b"ACGT"
 PROTEIN = b"ACDEFGHIKLMNPQRSTVWY"
@@ -143,6 +145,16 @@ def _load() -> ctypes.CDLL:
     lib.lcs_autotune.argtypes = [vp, P(lcs_pair), u64, P(lcs_alphabet), ctypes.c_uint32,
                                  P(lcs_tuning), P(ctypes.c_float)]
     lib.lcs_autotune.restype = i32
+    lib.lcs_similarity_batch.argtypes = [vp, P(lcs_pair), u64, P(lcs_alphabet),
+                                         P(ctypes.c_double)]
+    lib.lcs_similarity_batch.restype = i32
+    lib.lcs_threshold_batch.argtypes = [vp, P(lcs_pair), u64, P(lcs_alphabet), ctypes.c_double,
+                                        u8p, u64p]
+    lib.lcs_threshold_batch.restype = i32
+    lib.lcs_batch_set_threshold.argtypes = [vp, ctypes.c_double]
+    lib.lcs_batch_set_threshold.restype = i32
+    lib.lcs_batch_decisions.argtypes = [vp, u8p, u64p]
+    lib.lcs_batch_decisions.restype = i32
     lib.lcs_server_create.argtypes = [vp, P(lcs_server_config), P(vp)]
     lib.lcs_server_create.restype = i32
     lib.lcs_server_destroy.argtypes = [vp]
@@ -329,13 +341,40 @@ def lcs_traceback_batch(ctx: Context, pairs, alphabet="dna") -> List[bytes]:
     return [arena[int(o):int(o) + int(l)].tobytes() for o, l in zip(offs[:pp.count], lens[:pp.count])]
 
 
+def lcs_similarity_batch(ctx: Context, pairs, alphabet="dna") -> np.ndarray:
+    """Similarity percentages (100 * L) / |X| of each pair (100 for empty X)."""
+    pp = _Pairs(pairs)
+    al = _alpha(alphabet)
+    out = np.zeros(max(1, pp.count), dtype=np.float64)
+    _check(_lib.lcs_similarity_batch(ctx.h, pp.ptr(), pp.count, ctypes.byref(al.c),
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "lcs_similarity_batch")
+    return out[:pp.count]
+
+
+def lcs_threshold_batch(ctx: Context, pairs, min_percent: float,
+                        alphabet="dna") -> Tuple[np.ndarray, np.ndarray]:
+    """(pass, lengths): pass[k] is True when the similarity of pair k is at
+    least min_percent; lengths[k] is its LCS length, or LCS_LENGTH_UNKNOWN
+    when the answer came before the last column."""
+    pp = _Pairs(pairs)
+    al = _alpha(alphabet)
+    ok = np.zeros(max(1, pp.count), dtype=np.uint8)
+    lens = np.zeros(max(1, pp.count), dtype=np.uint64)
+    _check(_lib.lcs_threshold_batch(ctx.h, pp.ptr(), pp.count, ctypes.byref(al.c),
+                                    float(min_percent), _u8p(ok),
+                                    lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))),
+           "lcs_threshold_batch")
+    return ok[:pp.count].astype(bool), lens[:pp.count]
+
+
 class Batch:
     """A resident batch (``lcs_batch_create``): inputs uploaded once, run many times."""
 
     def __init__(self, ctx: Context, pairs, alphabet="dna", traceback: bool = False,
                  graph: bool = False, words_per_lane: int = 0, ckpt_interval: int = 0,
                  persistent_waves: int = 0, plain: bool = False, strip_rows: int = 0,
-                 tb_tiles: int = 0, tb_bands: int = 0):
+                 tb_tiles: int = 0, tb_bands: int = 0, threshold: Optional[float] = None):
         self.ctx = ctx
         self._pairs = _Pairs(pairs)
         self.count = self._pairs.count
@@ -343,6 +382,8 @@ class Batch:
         self.traceback = traceback
         self.cap = sum(min(len(_as_u8(x)), len(_as_u8(y))) for x, y in pairs)
         flags = (LCS_WANT_TRACEBACK if traceback else 0) | (LCS_USE_GRAPH if graph else 0)
+        if threshold is not None:
+            flags |= LCS_THRESHOLD
         t = _tuning(words_per_lane, ckpt_interval, persistent_waves, plain, strip_rows, tb_tiles,
                     tb_bands)
         h = ctypes.c_void_p()
@@ -352,6 +393,20 @@ class Batch:
         self.h = h
         # inputs are on the device now; host copies are no longer needed
         self._pairs = None
+        if threshold is not None:
+            self.set_threshold(threshold)
+
+    def set_threshold(self, min_percent: float) -> None:
+        _check(_lib.lcs_batch_set_threshold(self.h, float(min_percent)), "lcs_batch_set_threshold")
+
+    def decisions(self) -> Tuple[np.ndarray, np.ndarray]:
+        """(pass, lengths) of the last threshold pass, as lcs_threshold_batch."""
+        ok = np.zeros(max(1, self.count), dtype=np.uint8)
+        lens = np.zeros(max(1, self.count), dtype=np.uint64)
+        _check(_lib.lcs_batch_decisions(self.h, _u8p(ok),
+                                        lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))),
+               "lcs_batch_decisions")
+        return ok[:self.count].astype(bool), lens[:self.count]
 
     def run(self) -> None:
         _check(_lib.lcs_batch_run(self.h), "lcs_batch_run")

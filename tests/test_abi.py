@@ -69,6 +69,32 @@ def test_server_arguments_rejected_before_any_device_call():
     L.lcs_server_destroy(None)
 
 
+def test_threshold_arguments_and_flags_rejected_before_any_device_call():
+    L = lcs.lib()
+    al = lcs.lcs_alphabet(4, ctypes.cast(ctypes.c_char_p(b"ACGT"), ctypes.POINTER(ctypes.c_uint8)))
+    ok = (ctypes.c_uint8 * 1)()
+    n = (ctypes.c_uint64 * 1)()
+    pct = (ctypes.c_double * 1)()
+    assert L.lcs_threshold_batch(None, None, 0, ctypes.byref(al), 50.0, ok, n) == lcs.LCS_ERR_ARG
+    assert L.lcs_similarity_batch(None, None, 0, ctypes.byref(al), pct) == lcs.LCS_ERR_ARG
+    assert L.lcs_batch_set_threshold(None, 50.0) == lcs.LCS_ERR_ARG
+    assert L.lcs_batch_decisions(None, ok, n) == lcs.LCS_ERR_ARG
+    # the threshold pass plans like a lengths-only pass; never with a traceback
+    m = np.array([100, 9000], dtype=np.uint64)
+    P64 = ctypes.POINTER(ctypes.c_uint64)
+    s = lcs.lcs_batch_stats()
+    t = lcs.lcs_tuning()
+    mp = m.ctypes.data_as(P64)
+    assert L.lcs_plan_describe(mp, mp, 2, 4, lcs.LCS_THRESHOLD, ctypes.byref(t),
+                               ctypes.byref(s)) == lcs.LCS_OK
+    assert L.lcs_plan_describe(mp, mp, 2, 4, lcs.LCS_THRESHOLD | lcs.LCS_WANT_TRACEBACK,
+                               ctypes.byref(t), ctypes.byref(s)) == lcs.LCS_ERR_ARG
+    assert L.lcs_plan_describe(mp, mp, 2, 4, 8, ctypes.byref(t), ctypes.byref(s)) == lcs.LCS_ERR_ARG
+    best = lcs.lcs_tuning()
+    assert L.lcs_autotune(None, None, 0, ctypes.byref(al), lcs.LCS_THRESHOLD, ctypes.byref(best),
+                          None) == lcs.LCS_ERR_ARG
+
+
 def test_null_arguments_rejected_before_any_device_call():
     L = lcs.lib()
     out = ctypes.c_uint64(7)
