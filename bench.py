@@ -154,6 +154,41 @@ def serve_leg(lcs, ctx, rates, count: int):
 PAPER_TABLE1_SPEEDUP = {(5000, 200): 3.22, (10000, 1500): 2.89}
 
 
+def threshold_leg(lcs, ctx, pairs, alpha, reps: int = 5):
+    """Section II's yes/no question (lengths only), graph-replayed threshold
+    passes at three thresholds against the lengths-only pass of the same
+    pairs, with the share of pairs whose answer came before their last
+    column.  Two pair sets: the workload's own pairs, and a screening set --
+    the same parents, every other child replaced by an unrelated random
+    string of the same length (seeded)."""
+    g = np.random.default_rng(13064627 + 61)
+    symbols = np.frombuffer(lcs.DNA if alpha == "dna" else lcs.PROTEIN, dtype=np.uint8)
+    screen = [(x, symbols[g.integers(0, symbols.size, len(y))] if k % 2 else y)
+              for k, (x, y) in enumerate(pairs)]
+    out = {}
+    for name, ps in (("workload", pairs), ("screening", screen)):
+        cells = float(sum(len(x) * len(y) for x, y in ps))
+        with lcs.Batch(ctx, ps, alpha, graph=True) as lb:
+            lb.time()
+            base = float(np.median([lb.time()[0] for _ in range(reps)]))
+        leg = {"lengths_only_ms": round(base, 4), "passes": []}
+        with lcs.Batch(ctx, ps, alpha, graph=True, threshold=90.0) as tb:
+            for pct in (80.0, 90.0, 95.0):
+                tb.set_threshold(pct)
+                tb.time()
+                ms = float(np.median([tb.time()[0] for _ in range(reps)]))
+                ok, lens = tb.decisions()
+                leg["passes"].append({
+                    "min_percent": pct, "ms": round(ms, 4),
+                    "speedup_vs_lengths": round(base / ms, 2),
+                    "pass_share": round(float(ok.mean()), 4),
+                    "answered_early_share": round(float((lens == lcs.LCS_LENGTH_UNKNOWN).mean()), 4),
+                    "effective_GCUPS": round(cells / (ms * 1e-3) / 1e9, 1)})
+                log(f"threshold {name} {pct}%: {ms:.3f} ms vs lengths-only {base:.3f} ms")
+        out[name] = leg
+    return out
+
+
 def striped_leg(lcs, ctx, cores: int):
     """The paper's row-striped OpenMP method on this host at Table-1 shapes
     and at 4096 x 4096, on 1, 4 and all threads, beside one GPU pass over the
@@ -189,6 +224,7 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-pair leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server leg")
+    ap.add_argument("--no-threshold", action="store_true", help="skip the threshold-pass leg")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-only", action="store_true",
                     help="only run the request-server leg and print its results")
@@ -290,6 +326,9 @@ def main() -> int:
         out["plain_per_pair"] = {"value": round(cells / (t_plain * 1e-3) / 1e9, 2), "unit": "GCUPS",
                                  "ms": round(t_plain, 3)}
         out["batched_over_plain"] = round(value / out["plain_per_pair"]["value"], 2)
+    if not args.no_threshold:
+        log("threshold-pass leg")
+        out["threshold"] = threshold_leg(lcs, ctx, pairs, alpha)
     if not args.no_serve:
         log("request-server leg")
         out["serving"] = {"workload": "Poisson arrivals; |X|, |Y| log-uniform [100, 100000]; "

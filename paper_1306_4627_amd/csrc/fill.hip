@@ -147,21 +147,24 @@ __device__ __forceinline__ uint32_t clamp_col(int64_t j, uint32_t n) {
 // with RAW the plain code, shifted here.
 //
 // MODE kFillThreshold (section II's yes/no question: does the child keep at
-// least a given share of the parent?): at the start of every chunk each lane
-// counts the zero bits of its rows, the counts are summed per pair segment of
-// the wave, and a chained item adds the running sum handed up by the item
-// below (taken at the start of that item's previous chunk) and hands the new
-// sum up with its carries.  The one-chunk delay per item offsets the item's
-// 64 extra steps of skew, so the sum H seen by a pair's top lane covers every
-// row block at columns falling by one per lane from Jb (bottom lane) to J
-// (top lane).  Column steps raise c by at most one, hence
+// least a given share of the parent?): at the start of every kThrEvery-th
+// chunk each lane counts the zero bits of its rows, the counts are summed per
+// pair segment of the wave, and a chained item adds the running sum handed up
+// by the item below (taken at the start of that item's previous chunk) and
+// hands the new sum up with its carries.  Item h of a chain checks at the
+// chunks c with c = h (mod kThrEvery), so its feeder checked at chunk c - 1.
+// The one-chunk delay per item offsets the item's 64 extra steps of skew, so
+// the sum H seen by a pair's top lane covers every row block at columns
+// falling by one per lane from Jb (bottom lane) to J (top lane).  Column steps raise c by at most one, hence
 // H - (Jb - J) <= c[m][J] <= H, and since c[m][n] >= c[m][J] and
 // c[m][n] <= c[m][J] + (n - J), the pair reaches its target T once
 // H - (Jb - J) >= T and cannot once H + (n - J) < T.  The top lane then
 // records the answer; a wave whose pairs are all answered stops, and so do
 // the items of a chain once its pair is.
+constexpr uint32_t kThrEvery = 4;   // chunks between threshold checks of an item
+
 template <int WPL, int MODE, bool RAW>
-__global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
+__device__ __forceinline__ void fill_body(const FillArgs &a) {
     constexpr bool TB = MODE == kFillTraceback;
     constexpr bool THR = MODE == kFillThreshold;
     extern __shared__ uint64_t smem[];
@@ -192,6 +195,13 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
         const int32_t prev = a.it_prev[item];
         const bool feeds = a.it_feeds[item] != 0;
 
+        // the first two groups of stream values are requested now: their
+        // latency overlaps the match-mask build
+        const uint16_t *ys = a.ystream + ysoff - skew;
+        uint32_t Y0[8], Y1[8], Y2[8], Y3[8];
+        load16(ys, 0, Y0);
+        load16(ys, 16, Y1);
+
         // ---- match masks of this lane's rows (LDS, own column only) ----
         for (int c = 0; c < sig1; ++c)
 #pragma unroll
@@ -205,18 +215,27 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
                 if (row0 >= m) break;
                 uint64_t *col = pm + q * 64 + lane;
                 const uint32_t cnt = (m - row0) < 64u ? (m - row0) : 64u;
+                // the word's 64 codes with four 16-byte loads issued together
+                // (each sequence starts 64-byte aligned in the X arena and is
+                // padded to a multiple of 64 bytes)
+                // (walked with a run-time counter: fully unrolled, the 64 row
+                // bits become constants hoisted out of the item loop)
+                const uint4 *src = (const uint4 *)(xc + row0);
+                const uint4 d0 = src[0], d1 = src[1], d2 = src[2], d3 = src[3];
 #pragma unroll 1
-                for (uint32_t r0 = 0; r0 < cnt; r0 += 4) {
-                    // the X arena is padded to 64 bytes per sequence
-                    const uint32_t w4 = *(const uint32_t *)(xc + row0 + r0);
+                for (uint32_t k = 0; k < 4; ++k) {
+                    const uint4 dk = k == 0 ? d0 : k == 1 ? d1 : k == 2 ? d2 : d3;
+                    const uint32_t w[4] = {dk.x, dk.y, dk.z, dk.w};
 #pragma unroll
-                    for (int by = 0; by < 4; ++by) {
-                        const uint32_t r = r0 + by;
-                        if (r < cnt) {
-                            const uint32_t c = (w4 >> (8 * by)) & 0xffu;
-                            atomicOr((unsigned long long *)(col + c * RS), 1ull << r);
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int by = 0; by < 4; ++by) {
+                            const uint32_t r = 16 * k + 4 * e + by;
+                            if (r < cnt) {
+                                const uint32_t c = (w[e] >> (8 * by)) & 0xffu;
+                                atomicOr((unsigned long long *)(col + c * RS), 1ull << r);
+                            }
                         }
-                    }
                 }
             }
         }
@@ -225,7 +244,6 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
         uint32_t vlo[WPL], vhi[WPL];
 #pragma unroll
         for (int q = 0; q < WPL; ++q) { vlo[q] = ~0u; vhi[q] = ~0u; }
-        const uint16_t *ys = a.ystream + ysoff - skew;
         const uint64_t startmask = __builtin_amdgcn_ballot_w64(pair < 0 || word0 == 0);
         const uint64_t notstart = ~startmask;
         uint64_t cmask = 0;
@@ -256,7 +274,11 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
         bool seg_top = false;
         uint32_t nq = 0, tq = 0, pdec = 0, pdec_nx = 0;
         bool live_in = prev >= 0;
+        // check phase: the item's place in its chain (lane 0's skew is
+        // h * (kLanes - 1 + kChunk) in item h of a chain, 0 elsewhere)
+        uint32_t phase = 0;
         if (THR) {
+            phase = (__builtin_amdgcn_readfirstlane(skew) / (uint32_t)(kLanes - 1 + kChunk)) % kThrEvery;
             const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
             seg0 = 63 - __builtin_clzll((startmask | 1ull) & upto);
             const int32_t pair_up = __shfl(pair, lane == 63 ? 63 : lane + 1);
@@ -268,12 +290,10 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
             pdec = load_state(a.thr_dec, pair);
         }
         bool aborted = false, stopped = false;
-        // Stream values, two per dword, in a ring of four 16-step groups; the
-        // group 32 steps ahead is requested before the current one is used,
-        // so the stream's memory latency hides behind two groups of work.
-        uint32_t Y0[8], Y1[8], Y2[8], Y3[8];
-        load16(ys, 0, Y0);
-        load16(ys, 16, Y1);
+        // Stream values, two per dword, in a ring of four 16-step groups (the
+        // first two were requested above); the group 32 steps ahead is
+        // requested before the current one is used, so the stream's memory
+        // latency hides behind two groups of work.
         const bool chain = prev >= 0 || feeds;
         // The longest items bound the kernel's duration: let the SIMD issue
         // their instructions first; shorter items fill the remaining slots.
@@ -287,8 +307,10 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
             if (live_in && c > 0) {
                 uint64_t w0 = uniform64(pw0), w1 = uniform64(pw1), w2 = THR ? uniform64(pw2) : 0;
                 uint32_t spins = 0;
+                // (the running sum is handed up only for this item's check chunks)
+                const bool want_sum = THR && (c + kThrEvery - phase) % kThrEvery == 0;
                 while ((uint32_t)(w0 >> 32) != c || (uint32_t)(w1 >> 32) != c ||
-                       (THR && (uint32_t)(w2 >> 32) != c)) {
+                       (want_sum && (uint32_t)(w2 >> 32) != c)) {
                     // bounded wait for the feeding item to finish chunk c-1
                     if (++spins > a.spin_limit) { aborted = true; break; }
                     if (THR) {
@@ -303,7 +325,7 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
                                                      __HIP_MEMORY_SCOPE_AGENT));
                     w1 = uniform64(__hip_atomic_load(xf_in + 2 * (c - 1) + 1, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT));
-                    if (THR)
+                    if (want_sum)
                         w2 = uniform64(__hip_atomic_load(xs_in + (c - 1), __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT));
                 }
@@ -314,9 +336,13 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
             }
             const uint32_t t = c * 64u;
             uint32_t hout = 0;
+            // this item's check chunks; its sum word is handed up at each of
+            // them (at chunk 0 it is 0: no column is done yet)
+            const bool sum_chunk = THR && (c + kThrEvery - phase) % kThrEvery == 0;
+            const bool check = sum_chunk && c > 0;
             if (THR) {
                 if (!pdec) pdec = pdec_nx;
-                if (c > 0) {
+                if (check) {
                     // segment sums of the zero counts (LDS, in wave order)
                     const uint32_t z = lane_zeros<WPL>(vlo, vhi, pair, word0, m);
                     tslot[lane] = 0;
@@ -377,7 +403,7 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
                     pw0 = __hip_atomic_load(xf_in + 2 * c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     pw1 = __hip_atomic_load(xf_in + 2 * c + 1, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
-                    if (THR)
+                    if (THR && (c + 1 + kThrEvery - phase) % kThrEvery == 0)
                         pw2 = __hip_atomic_load(xs_in + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
                 if (THR) pdec_nx = load_state(a.thr_dec, pair);
@@ -392,7 +418,7 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     __hip_atomic_store(xf_out + 2 * c + 1, tag | (outbits >> 32), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-                    if (THR)
+                    if (sum_chunk)
                         __hip_atomic_store(xs_out + c, tag | hout, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
@@ -422,12 +448,37 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
     }
 }
 
+// Kernel entry points.  Left to itself the compiler gives the threshold mode
+// about 150 VGPRs at two words per lane (three waves per SIMD); held to 128
+// at one or two words per lane it keeps four waves like the lengths-only
+// fill, and the values that then spill belong to the per-item set-up and the
+// threshold checks, not to the column steps (5% faster on the 4096-pair
+// related batch).  The traceback mode (132 VGPRs) measured 5% slower when
+// held to 128, and wider lanes would spill inside the steps: both keep the
+// unconstrained entry.
+template <int WPL, int MODE, bool RAW>
+__global__ __launch_bounds__(kFillBlock) void k_fill(FillArgs a) {
+    fill_body<WPL, MODE, RAW>(a);
+}
+
+template <int WPL, int MODE, bool RAW>
+__global__ __launch_bounds__(kFillBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_fill4(FillArgs a) {
+    fill_body<WPL, MODE, RAW>(a);
+}
+
+template <int WPL, int MODE, bool RAW>
+static const void *fill_entry() {
+    if constexpr (WPL <= 2 && MODE == kFillThreshold) return (const void *)&k_fill4<WPL, MODE, RAW>;
+    else return (const void *)&k_fill<WPL, MODE, RAW>;
+}
+
 const void *fill_symbol(int wpl, int mode, bool raw) {
-#define LCS_FILL_SYM(W, R)                                                   \
-    if (wpl == W && raw == R) {                                              \
-        if (mode == kFillTraceback) return (const void *)&k_fill<W, kFillTraceback, R>; \
-        if (mode == kFillThreshold) return (const void *)&k_fill<W, kFillThreshold, R>; \
-        return (const void *)&k_fill<W, kFillLength, R>;                     \
+#define LCS_FILL_SYM(W, R)                                                              \
+    if (wpl == W && raw == R) {                                                         \
+        if (mode == kFillTraceback) return fill_entry<W, kFillTraceback, R>();          \
+        if (mode == kFillThreshold) return fill_entry<W, kFillThreshold, R>();          \
+        return fill_entry<W, kFillLength, R>();                                         \
     }
     LCS_FILL_SYM(1, false)
     LCS_FILL_SYM(2, false)
@@ -445,27 +496,12 @@ hipError_t launch_fill(int wpl, int mode, const FillArgs &a, uint32_t grid, hipS
     if (!wpl_fits(a.sigma, wpl)) return hipErrorInvalidValue;
     if (mode == kFillThreshold && (!a.pair_n || !a.thr_t || !a.thr_dec || !a.xsum))
         return hipErrorInvalidValue;
-    const size_t lds = fill_lds_bytes(wpl, a.sigma, mode);
-    const dim3 block((uint32_t)fill_block(wpl, a.sigma));
-    const bool raw = raw_stream(a.sigma, wpl);
-#define LCS_FILL_CASE(W, R)                                                                  \
-    if (wpl == W && raw == R) {                                                              \
-        if (mode == kFillTraceback)                                                          \
-            hipLaunchKernelGGL((k_fill<W, kFillTraceback, R>), dim3(grid), block, lds, s, a); \
-        else if (mode == kFillThreshold)                                                     \
-            hipLaunchKernelGGL((k_fill<W, kFillThreshold, R>), dim3(grid), block, lds, s, a); \
-        else                                                                                 \
-            hipLaunchKernelGGL((k_fill<W, kFillLength, R>), dim3(grid), block, lds, s, a);   \
-        return hipGetLastError();                                                            \
-    }
-    LCS_FILL_CASE(1, false)
-    LCS_FILL_CASE(2, false)
-    LCS_FILL_CASE(4, false)
-    LCS_FILL_CASE(8, false)
-    LCS_FILL_CASE(1, true)
-    LCS_FILL_CASE(2, true)
-#undef LCS_FILL_CASE
-    return hipErrorInvalidValue;
+    const void *fn = fill_symbol(wpl, mode, raw_stream(a.sigma, wpl));
+    if (!fn) return hipErrorInvalidValue;
+    FillArgs arg = a;
+    void *args[] = {&arg};
+    return hipLaunchKernel(fn, dim3(grid), dim3((uint32_t)fill_block(wpl, a.sigma)), args,
+                           fill_lds_bytes(wpl, a.sigma, mode), s);
 }
 
 }  // namespace lcs

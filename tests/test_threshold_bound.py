@@ -3,8 +3,9 @@ oracle's full c table (section I.C).
 
 The fill keeps the rows of a pair in blocks (one block per lane), lanes in
 work items of G lanes, and runs lane l of item h with a skew of
-h*(G-1+C) + l steps (C steps per chunk).  At the start of chunk c an item
-adds the zero bits of its lanes (block k at column j holds
+h*(G-1+C) + l steps (C steps per chunk).  At the start of chunk c (every
+E-th chunk, item h at the chunks c = h mod E) an item adds the zero bits of
+its lanes (block k at column j holds
 c[top_k][j] - c[bottom_k - 1][j] of them) to the running sum handed up from
 the item below at the start of the previous chunk.  The pair's top lane then
 knows a sum H and two columns: J, its own, and Jb, the bottom lane's at the
@@ -28,8 +29,11 @@ def _clamp(j, n):
     return min(max(j, 0), n)
 
 
-def _snapshots(c_tab, R, G, C):
-    """(H, J, Jb) at the start of every chunk, as the top lane sees them."""
+def _snapshots(c_tab, R, G, C, E=1):
+    """(H, J, Jb) at the chunks where the top item checks, as its top lane
+    sees them.  Item h forms its sum only at the chunks c = h (mod E), from
+    the sum its feeder formed at chunk c - 1 (which must exist: a KeyError
+    here would mean the schedule hands up a sum that was never formed)."""
     m, n = c_tab.shape[0] - 1, c_tab.shape[1] - 1
     lanes = -(-m // R)
     K, l_top = (lanes - 1) // G, (lanes - 1) % G
@@ -46,12 +50,16 @@ def _snapshots(c_tab, R, G, C):
     out = []
     for c in range(nch):
         for h in range(K + 1):
+            if (c - h) % E:
+                continue
             s = sum(zeros(h * G + l, C * c - (h * step + l))
                     for l in range(G) if h * G + l < lanes)
-            H[h, c] = s + (H.get((h - 1, c - 1), 0) if h > 0 else 0)
-        J = _clamp(C * c - (K * step + l_top), n)
-        Jb = _clamp(C * (c - K), n)
-        out.append((H[K, c], J, Jb))
+            # below chunk 0 nothing has been handed up yet
+            H[h, c] = s + (H[h - 1, c - 1] if h > 0 and c > 0 else 0)
+        if (c - K) % E == 0:
+            J = _clamp(C * c - (K * step + l_top), n)
+            Jb = _clamp(C * (c - K), n)
+            out.append((H[K, c], J, Jb))
     return out
 
 
@@ -70,13 +78,14 @@ def _pairs(seed, count):
     return out
 
 
-@pytest.mark.parametrize("R,G,C", [(1, 1, 1), (3, 2, 4), (8, 4, 8), (5, 3, 2), (2, 4, 1),
-                                   (16, 2, 16)])
-def test_staircase_sum_brackets_the_top_row(R, G, C):
-    for x, y in _pairs(900 + 7 * R + G + C, 40):
+@pytest.mark.parametrize("R,G,C,E", [(1, 1, 1, 1), (3, 2, 4, 1), (8, 4, 8, 1), (5, 3, 2, 1),
+                                     (2, 4, 1, 1), (16, 2, 16, 1), (3, 2, 4, 4), (2, 3, 2, 3),
+                                     (4, 2, 2, 4)])
+def test_staircase_sum_brackets_the_top_row(R, G, C, E):
+    for x, y in _pairs(900 + 7 * R + G + C + E, 40):
         c_tab, _ = oracle.lcs_tables(x, y)
         m = len(x)
-        for H, J, Jb in _snapshots(c_tab, R, G, C):
+        for H, J, Jb in _snapshots(c_tab, R, G, C, E):
             assert 0 <= Jb - J
             assert H - (Jb - J) <= int(c_tab[m, J]) <= H, (len(x), len(y), H, J, Jb)
             if J == Jb == len(y):
@@ -84,15 +93,15 @@ def test_staircase_sum_brackets_the_top_row(R, G, C):
                 assert H == int(c_tab[m, len(y)])
 
 
-@pytest.mark.parametrize("R,G,C", [(4, 2, 4), (8, 4, 8), (2, 3, 2)])
-def test_early_answers_are_final_and_happen(R, G, C):
+@pytest.mark.parametrize("R,G,C,E", [(4, 2, 4, 1), (8, 4, 8, 1), (2, 3, 2, 1), (2, 3, 2, 4)])
+def test_early_answers_are_final_and_happen(R, G, C, E):
     early = 0
     total = 0
-    for x, y in _pairs(1900 + R + G + C, 40):
+    for x, y in _pairs(1900 + R + G + C + E, 40):
         c_tab, _ = oracle.lcs_tables(x, y)
         m, n = len(x), len(y)
         L = int(c_tab[m, n])
-        snaps = _snapshots(c_tab, R, G, C)
+        snaps = _snapshots(c_tab, R, G, C, E)
         for T in range(0, min(m, n) + 1):
             for k, (H, J, Jb) in enumerate(snaps):
                 yes = H - (Jb - J) >= T
