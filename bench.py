@@ -247,8 +247,9 @@ def main() -> int:
         print(json.dumps({"calibration_copy_bytes": args.calibrate_copy}), flush=True)
         return 0
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the workload is the one-GPU "
-              "share); --gpus must be 1", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU (its workload is one GPU's share; "
+              "pairs are independent, so batches shard by pair); --gpus must be 1",
+              file=sys.stderr)
         return 2
 
     from paper_1306_4627_amd import lcs

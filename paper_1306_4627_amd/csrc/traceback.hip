@@ -159,8 +159,11 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
             const int32_t guess = guess_raw < 1u ? 1 : (int32_t)guess_raw;
             int32_t i = top, j = 0;
             bool walk = true;
-            const bool rec = a.mode == kTbSpec;    // record band crossings
-            const bool cmp = a.mode == kTbFix;     // stop where the speculative walk is met
+            // every pass records the columns where its walk leaves each band,
+            // so `cross` always describes the path now in the bitmap; the
+            // fix-up and seal passes stop where their walk meets that path
+            // (from the same position the walks coincide)
+            const bool cmp = a.mode != kTbSpec;
             if (a.mode == kTbSpec) {
                 if (s == S - 1) {
                     i = (int32_t)m;
@@ -463,11 +466,11 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
                         if (lane == 0) dg[dwi] = dword;
                         dwi = -1;
                         dword = 0;
-                        if (rec && lane == 0) cross[ell] = (uint32_t)j;
                         if (cmp && (int32_t)cross[ell] == j) {
                             merged = true;
                             break;
                         }
+                        if (lane == 0) cross[ell] = (uint32_t)j;
                     }
                 }
                 if (!merged) {
@@ -475,11 +478,10 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
                     if (j == 0 && i > i_stop) {
                         // the walk ended inside the strip: rows i_stop+1..i
                         // take no diagonal step
-                        if (rec)
-                            for (int32_t g = i_stop / (int32_t)BAND + lane; g <= (i - 1) / (int32_t)BAND;
-                                 g += 64)
-                                cross[g] = 0;
-                        if (!rec)
+                        for (int32_t g = i_stop / (int32_t)BAND + lane; g <= (i - 1) / (int32_t)BAND;
+                             g += 64)
+                            cross[g] = 0;
+                        if (cmp)
                             for (int32_t w = i_stop / 64 + lane; w < i / 64; w += 64) dg[w] = 0;
                     }
                 }
@@ -490,7 +492,9 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
                     sres[2 * s + 1] = (!walk || merged) ? cross[s * G] : (uint32_t)j;
                 }
             } else if (a.mode == kTbSeal) {
-                e = walk ? j : (int32_t)sres[2 * s + 1];
+                // a walk that met the recorded path leaves the strip where
+                // that path does
+                e = !walk ? (int32_t)sres[2 * s + 1] : merged ? (int32_t)cross[s * G] : j;
             }
             if (a.mode != kTbSeal || s == 0) break;
             --s;

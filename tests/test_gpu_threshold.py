@@ -205,3 +205,31 @@ def test_threshold_related_workload_4096(ctx, lcs):
             assert (lens[known] <= np.minimum(m, n)[known]).all()
             pk = (100.0 * lens[known].astype(np.float64)) / m[known]
             assert np.array_equal(ok[known], pk >= pct)
+
+
+@pytest.mark.parametrize("sigma", [20, 150, 256])
+def test_threshold_wide_alphabets(ctx, lcs, sigma):
+    # protein codes, and alphabets whose stream holds plain codes (above 127
+    # symbols at one or two words per lane): short, single-wave and chained
+    # pairs, related and unrelated
+    g = inputs.rng(8300 + sigma)
+    syms = inputs.PROTEIN if sigma == 20 else bytes(range(sigma))
+    alpha = "protein" if sigma == 20 else (None if sigma == 256 else syms)
+    pairs = []
+    for k, m in enumerate([40, 300, 900, 2500, 6000, 9000, 17000]):
+        x = inputs.random_seq(g, m, syms)
+        if k % 2:
+            y, _ = inputs.mutate(g, x, float(g.uniform(0.05, 0.4)), syms)
+        else:
+            y = inputs.random_seq(g, m, syms)
+        pairs.append((x.tobytes(), y.tobytes()))
+    sim, L = _similarity(pairs), _lengths(pairs)
+    # (at 256 symbols two words per lane need more LDS than a work-group has)
+    for wpl in ((1,) if sigma == 256 else (1, 2)):
+        with lcs.Batch(ctx, pairs, alpha, threshold=50.0, words_per_lane=wpl) as b:
+            for pct in (5.0, 50.0, 80.0, 95.0):
+                _say(f"threshold sigma={sigma} wpl={wpl} pct={pct}")
+                b.set_threshold(pct)
+                b.run()
+                ok, lens = b.decisions()
+                _check(pairs, sim, L, pct, ok, lens)
