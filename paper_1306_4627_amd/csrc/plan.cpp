@@ -24,10 +24,23 @@ static inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b
 bool raw_stream(int sigma, int wpl) { return sigma * wpl > 127; }
 
 int fill_waves(int sigma, int wpl) {
-    const size_t per_wave = (size_t)(sigma + 1) * wpl * 512;
-    for (int w = 4; w >= 1; w >>= 1)
-        if ((size_t)w * per_wave <= 160 * 1024) return w;
-    return 0;
+    // LDS of one wave: its match masks ([symbol + sentinel][word][lane]) and
+    // the threshold pass's 128 words; the work-group size (4, 2 or 1 waves;
+    // the waves are independent) that keeps the most waves resident on a
+    // 160 KiB CU wins, up to 16 (four per SIMD, what the fill's registers
+    // allow), larger groups on ties
+    const size_t per_wave = (size_t)(sigma + 1) * wpl * 512 + 512;
+    const size_t lds = 160 * 1024;
+    int best = 0, best_res = 0;
+    for (int w = 4; w >= 1; w >>= 1) {
+        if ((size_t)w * per_wave > lds) continue;
+        const int res = std::min<int>((int)(lds / ((size_t)w * per_wave)) * w, 16);
+        if (res > best_res) {
+            best = w;
+            best_res = res;
+        }
+    }
+    return best;
 }
 
 bool wpl_fits(int sigma, int wpl) {

@@ -124,6 +124,12 @@ def test_plan_rejects_bad_tuning_and_alphabets():
     with pytest.raises(lcs.LcsError) as e:
         lcs.plan_describe(m, n, 256, words_per_lane=2)   # 257 x 1 KiB of match masks per wave
     assert e.value.status == lcs.LCS_ERR_UNSUPPORTED
+    # one wave's LDS is its match masks plus 512 bytes of threshold-pass
+    # words: 160 symbols x 1 KiB + 512 B no longer fits 160 KiB
+    assert lcs.plan_describe(m, n, 158, words_per_lane=2)["words_per_lane"] == 2
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.plan_describe(m, n, 159, words_per_lane=2)
+    assert e.value.status == lcs.LCS_ERR_UNSUPPORTED
     with pytest.raises(lcs.LcsError) as e:
         lcs.plan_describe(m, n, 20, words_per_lane=8)
     assert e.value.status == lcs.LCS_ERR_UNSUPPORTED
