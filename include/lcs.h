@@ -107,7 +107,16 @@ typedef struct lcs_batch lcs_batch;
  *                    worth, fewer for wide bands);
  *  tb_bands        : bands the traceback recomputes at once (1..16,
  *                    tb_tiles * tb_bands <= 64; default: as many, up to 4,
- *                    as fit about 10 KiB of LDS per wave). */
+ *                    as fit about 10 KiB of LDS per wave);
+ *  link_items      : a pair too long for one wavefront continues in the
+ *                    following work items, passing carries through memory;
+ *                    it may start in the free lanes of the item before it
+ *                    when the two need nearly the same number of column
+ *                    steps.  Items linked this way form a run whose items all
+ *                    wait on the one below; link_items caps a run's length
+ *                    (default 1: a long pair always starts a new item; on the
+ *                    4096-pair related batch 8-32 pack 6-8% fewer lane-steps
+ *                    but run no faster).  Results do not depend on it. */
 typedef struct {
     int32_t words_per_lane;
     int32_t ckpt_interval;
@@ -116,6 +125,7 @@ typedef struct {
     int32_t strip_rows;
     int32_t tb_tiles;
     int32_t tb_bands;
+    int32_t link_items;
 } lcs_tuning;
 
 /* What a batch was planned into (filled by lcs_batch_info). */

@@ -151,8 +151,9 @@ __device__ __forceinline__ uint32_t clamp_col(int64_t j, uint32_t n) {
 // chunk each lane counts the zero bits of its rows, the counts are summed per
 // pair segment of the wave, and a chained item adds the running sum handed up
 // by the item below (taken at the start of that item's previous chunk) and
-// hands the new sum up with its carries.  Item h of a chain checks at the
-// chunks c with c = h (mod kThrEvery), so its feeder checked at chunk c - 1.
+// hands the new sum up with its carries.  An item d places into its run of
+// linked chains checks at the chunks c with c = d (mod kThrEvery), so its
+// feeder checked at chunk c - 1.
 // The one-chunk delay per item offsets the item's 64 extra steps of skew, so
 // the sum H seen by a pair's top lane covers every row block at columns
 // falling by one per lane from Jb (bottom lane) to J (top lane).  Column steps raise c by at most one, hence
@@ -274,11 +275,11 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
         bool seg_top = false;
         uint32_t nq = 0, tq = 0, pdec = 0, pdec_nx = 0;
         bool live_in = prev >= 0;
-        // check phase: the item's place in its chain (lane 0's skew is
-        // h * (kLanes - 1 + kChunk) in item h of a chain, 0 elsewhere)
+        // check phase: the item's place in its run of linked chains (every
+        // feeder sits one place below the item it feeds)
         uint32_t phase = 0;
         if (THR) {
-            phase = (__builtin_amdgcn_readfirstlane(skew) / (uint32_t)(kLanes - 1 + kChunk)) % kThrEvery;
+            phase = a.it_depth[item] % kThrEvery;
             const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
             seg0 = 63 - __builtin_clzll((startmask | 1ull) & upto);
             const int32_t pair_up = __shfl(pair, lane == 63 ? 63 : lane + 1);
@@ -355,9 +356,11 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
                     hout = __builtin_amdgcn_readlane(h, 63);
                     if (seg_top && pdec == 0 && !(lane == 63 && feeds)) {
                         // this lane tops its pair: columns J (own) and Jb
-                        // (bottom lane, h items and as many chunks below)
+                        // (bottom lane, `below` item boundaries and as many
+                        // chunks earlier; lane g of a pair has a skew of g
+                        // plus kChunk - 1 per boundary below it)
                         const uint32_t J = clamp_col((int64_t)t - (int64_t)skew, nq);
-                        const uint32_t below = skew / (uint32_t)(kLanes - 1 + kChunk);
+                        const uint32_t below = (skew - word0 / WPL) / (uint32_t)(kChunk - 1);
                         const uint32_t Jb = clamp_col(64 * ((int64_t)c - (int64_t)below), nq);
                         uint32_t d = 0;
                         if ((uint64_t)h >= (uint64_t)tq + (Jb - J)) d = 1;

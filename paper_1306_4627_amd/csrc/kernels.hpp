@@ -46,6 +46,7 @@ struct FillArgs {
     const uint32_t *it_T;
     const int32_t *it_prev;
     const uint8_t *it_feeds;
+    const uint32_t *it_depth;  // items before this one in its run of linked chains
     const uint64_t *it_ck;
     const uint64_t *it_cb;
     const uint64_t *it_xf;

@@ -57,6 +57,7 @@ struct ClassDev {
     uint32_t *it_T = nullptr;
     int32_t *it_prev = nullptr;
     uint8_t *it_feeds = nullptr;
+    uint32_t *it_depth = nullptr;
     uint64_t *it_ck = nullptr, *it_cb = nullptr, *it_xf = nullptr;
     int32_t *ln_pair = nullptr;
     uint32_t *ln_word0 = nullptr, *ln_skew = nullptr;
@@ -229,6 +230,7 @@ static lcs_status check_tuning(const lcs_tuning *t) {
         t->ckpt_interval != 256)
         return LCS_ERR_ARG;
     if (t->persistent_waves < 0 || t->plain < 0 || t->plain > 1) return LCS_ERR_ARG;
+    if (t->link_items < 0) return LCS_ERR_ARG;
     if (t->strip_rows < 0 || t->tb_tiles < 0 || t->tb_tiles > 8 || t->tb_bands < 0 ||
         t->tb_bands > 16 || t->tb_tiles * t->tb_bands > 64)
         return LCS_ERR_ARG;
@@ -242,6 +244,7 @@ static void fill_plan_config(PlanConfig &cfg, int sigma, uint32_t flags, const l
     cfg.sigma = sigma;
     cfg.plain = t && t->plain;
     cfg.strip_rows = (t && t->strip_rows) ? t->strip_rows : 4096;
+    cfg.link_items = (t && t->link_items) ? t->link_items : 1;
 }
 
 static void stats_from_plan(const Plan &p, uint64_t npairs, lcs_batch_stats *out) {
@@ -410,6 +413,7 @@ static size_t carve(lcs_batch *b, char *base) {
         D.it_T = cv.take<uint32_t>(D.nitems);
         D.it_prev = cv.take<int32_t>(D.nitems);
         D.it_feeds = cv.take<uint8_t>(D.nitems);
+        D.it_depth = cv.take<uint32_t>(D.nitems);
         D.it_ck = cv.take<uint64_t>(D.nitems);
         D.it_cb = cv.take<uint64_t>(D.nitems);
         D.it_xf = cv.take<uint64_t>(D.nitems);
@@ -675,6 +679,7 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         UP(D.it_T, C.it_T.data(), C.it_T.size() * 4);
         UP(D.it_prev, C.it_prev.data(), C.it_prev.size() * 4);
         UP(D.it_feeds, C.it_feeds.data(), C.it_feeds.size());
+        UP(D.it_depth, C.it_depth.data(), C.it_depth.size() * 4);
         UP(D.it_ck, C.it_ck.data(), C.it_ck.size() * 8);
         UP(D.it_cb, C.it_cb.data(), C.it_cb.size() * 8);
         UP(D.it_xf, C.it_xf.data(), C.it_xf.size() * 8);
@@ -819,6 +824,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         fa.it_T = D.it_T;
         fa.it_prev = D.it_prev;
         fa.it_feeds = D.it_feeds;
+        fa.it_depth = D.it_depth;
         fa.it_ck = D.it_ck;
         fa.it_cb = D.it_cb;
         fa.it_xf = D.it_xf;

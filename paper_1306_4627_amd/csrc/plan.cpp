@@ -122,12 +122,17 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
         });
         int64_t cur_item = -1;
         int cur_lane = kLanes;
+        // the run of items linked by carry hand-over that ends with cur_item:
+        // its largest step need and its length in items
+        uint64_t run_need = 0;
+        int run_len = 0;
         // segments of each item, to set T afterwards
         std::vector<std::vector<uint32_t>> item_segs;   // indices into pend
         auto new_item = [&](int32_t prev) {
             C.it_T.push_back(0);
             C.it_prev.push_back(prev);
             C.it_feeds.push_back(0);
+            C.it_depth.push_back(prev >= 0 ? C.it_depth[prev] + 1 : 0);
             for (int l = 0; l < kLanes; ++l) {
                 C.ln_pair.push_back(-1);
                 C.ln_word0.push_back(0);
@@ -146,7 +151,10 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
                 if (cur_item < 0 || cur_lane + (int)s > kLanes || (cfg.plain && cur_lane > 0)) {
                     cur_item = new_item(-1);
                     cur_lane = 0;
+                    run_need = 0;
+                    run_len = 1;
                 }
+                run_need = std::max<uint64_t>(run_need, p.n + s);
                 for (uint64_t l = 0; l < s; ++l) {
                     size_t li = (size_t)cur_item * kLanes + cur_lane + l;
                     C.ln_pair[li] = (int32_t)k;
@@ -160,32 +168,57 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
                 item_segs[cur_item].push_back(seg_id);
                 cur_lane += (int)s;
             } else {
-                const uint64_t H = ceil_div(s, kLanes);
-                int64_t first = -1, prev = -1;
-                for (uint64_t h = 0; h < H; ++h) {
-                    int64_t it = new_item((int32_t)prev);
-                    if (h == 0) first = it;
-                    if (prev >= 0) C.it_feeds[prev] = 1;
-                    uint64_t nl = std::min<uint64_t>(kLanes, s - h * kLanes);
-                    for (uint64_t l = 0; l < nl; ++l) {
-                        size_t li = (size_t)it * kLanes + l;
-                        uint64_t pos = h * kLanes + l;
-                        C.ln_pair[li] = (int32_t)k;
-                        C.ln_word0[li] = (uint32_t)(pos * wpl);
-                        C.ln_skew[li] = (uint32_t)(h * (kLanes - 1 + kChunk) + l);
-                    }
-                    item_segs[it].push_back(seg_id);
-                    prev = it;
-                    cur_item = it;
-                    cur_lane = (int)nl;
+                // A chain: lane g of the pair (words g*wpl..) sits g lanes
+                // above its first lane, crossing into the next item after lane
+                // 63, with a skew of g plus kChunk - 1 per item boundary
+                // crossed (lane 0 of the next item takes lane 63's carry of
+                // the chunk before, through memory).  It starts in the free
+                // lanes of the current item when its step need is close to
+                // that of the items already linked to it and the linked run
+                // stays within link_items; else in a new item.
+                auto need_at = [&](uint64_t l0) {
+                    const uint64_t g = s - 1, q = (g + l0) / kLanes;
+                    return p.n + g + (uint64_t)(kChunk - 1) * q + 1;
+                };
+                uint64_t l0 = 0;
+                if (!cfg.plain && cur_item >= 0 && cur_lane < kLanes) {
+                    const uint64_t need = need_at((uint64_t)cur_lane);
+                    const uint64_t extra = ceil_div(s - (uint64_t)(kLanes - cur_lane), kLanes);
+                    if ((double)need >= (1.0 - kLinkSpread) * (double)run_need &&
+                        (double)need <= (1.0 + kLinkSpread) * (double)run_need &&
+                        (uint64_t)run_len + extra <= (uint64_t)std::max(cfg.link_items, 1))
+                        l0 = (uint64_t)cur_lane;
                 }
-                uint64_t last_pos = s - 1;
-                uint64_t hl = last_pos / kLanes;
-                uint32_t pre = (uint32_t)(hl * (kLanes - 1 + kChunk) + (last_pos % kLanes));
+                int64_t it = cur_item;
+                if (l0 == 0) {
+                    it = new_item(-1);
+                    run_need = 0;
+                    run_len = 1;
+                }
+                const int64_t first = it;
+                uint64_t lane = l0, q = 0;
+                for (uint64_t g = 0; g < s; ++g, ++lane) {
+                    if (lane == (uint64_t)kLanes) {
+                        C.it_feeds[it] = 1;
+                        it = new_item((int32_t)it);
+                        ++run_len;
+                        lane = 0;
+                        ++q;
+                    }
+                    const size_t li = (size_t)it * kLanes + lane;
+                    C.ln_pair[li] = (int32_t)k;
+                    C.ln_word0[li] = (uint32_t)(g * wpl);
+                    C.ln_skew[li] = (uint32_t)(g + (uint64_t)(kChunk - 1) * q);
+                    if (g == 0 || lane == 0) item_segs[it].push_back(seg_id);
+                }
+                const uint32_t pre = (uint32_t)(need_at(l0) - p.n - 1);
+                run_need = std::max<uint64_t>(run_need, p.n + pre + 1);
                 C.tb_pair.push_back(k);
                 C.tb_item.push_back((uint32_t)first);
-                C.tb_lane0.push_back(0);
-                pend.push_back({k, pre, (uint32_t)cur_item, (uint32_t)ci});
+                C.tb_lane0.push_back((uint32_t)l0);
+                pend.push_back({k, pre, (uint32_t)it, (uint32_t)ci});
+                cur_item = it;
+                cur_lane = (int)lane;
                 if (cfg.plain) cur_lane = kLanes;
             }
         }
@@ -331,6 +364,8 @@ std::string check_plan(const std::vector<PairShape> &pairs, const Plan &p) {
             if (C.it_prev[it] >= 0 && C.it_prev[it] != (int32_t)it - 1) return "chain not consecutive";
             if (C.it_prev[it] >= 0 && !C.it_feeds[it - 1]) return "chain feed flag";
             if (C.it_prev[it] >= 0 && C.it_T[it] != C.it_T[it - 1]) return "chain step counts differ";
+            if (C.it_depth[it] != (C.it_prev[it] >= 0 ? C.it_depth[it - 1] + 1 : 0u))
+                return "chain depth";
             for (int l = 0; l < kLanes; ++l) {
                 size_t li = it * kLanes + l;
                 int32_t pr = C.ln_pair[li];

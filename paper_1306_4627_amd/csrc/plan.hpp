@@ -44,7 +44,13 @@ struct PlanConfig {
     int sigma = 4;          // alphabet size; code sigma is the zero-mask sentinel
     bool plain = false;     // one pair per item, no packing
     int strip_rows = 4096;  // rows per traceback strip (rounded up to whole bands)
+    int link_items = 1;     // items one run of linked chains may span (1 = no sharing)
 };
+
+// A chain may start in the free lanes of the item before it when its step
+// count is within this share of the largest one of the items linked to that
+// item (they all run for the largest).
+constexpr double kLinkSpread = 0.02;
 
 // One class = one fill launch with a fixed words-per-lane.
 struct ClassPlan {
@@ -53,6 +59,7 @@ struct ClassPlan {
     std::vector<uint32_t> it_T;       // steps, multiple of kChunk
     std::vector<int32_t> it_prev;     // item feeding lane 0 through memory, or -1
     std::vector<uint8_t> it_feeds;    // 1 if lane 63 continues into the next item
+    std::vector<uint32_t> it_depth;   // items before this one in its run of linked chains
     std::vector<uint64_t> it_ck;      // checkpoint base (uint64 units)
     std::vector<uint64_t> it_cb;      // carry-bit base (uint32 units)
     std::vector<uint64_t> it_xf;      // carry hand-over base (uint64 units, 2 per chunk), for feeders

@@ -59,7 +59,7 @@ class lcs_tuning(ctypes.Structure):
     _fields_ = [("words_per_lane", ctypes.c_int32), ("ckpt_interval", ctypes.c_int32),
                 ("persistent_waves", ctypes.c_int32), ("plain", ctypes.c_int32),
                 ("strip_rows", ctypes.c_int32), ("tb_tiles", ctypes.c_int32),
-                ("tb_bands", ctypes.c_int32)]
+                ("tb_bands", ctypes.c_int32), ("link_items", ctypes.c_int32)]
 
 
 class lcs_server_config(ctypes.Structure):
@@ -239,9 +239,9 @@ def _alpha(a) -> Alphabet:
 
 
 def _tuning(words_per_lane=0, ckpt_interval=0, persistent_waves=0, plain=False, strip_rows=0,
-            tb_tiles=0, tb_bands=0):
+            tb_tiles=0, tb_bands=0, link_items=0):
     return lcs_tuning(int(words_per_lane), int(ckpt_interval), int(persistent_waves), int(bool(plain)),
-                      int(strip_rows), int(tb_tiles), int(tb_bands))
+                      int(strip_rows), int(tb_tiles), int(tb_bands), int(link_items))
 
 
 class _Pairs:
@@ -374,7 +374,8 @@ class Batch:
     def __init__(self, ctx: Context, pairs, alphabet="dna", traceback: bool = False,
                  graph: bool = False, words_per_lane: int = 0, ckpt_interval: int = 0,
                  persistent_waves: int = 0, plain: bool = False, strip_rows: int = 0,
-                 tb_tiles: int = 0, tb_bands: int = 0, threshold: Optional[float] = None):
+                 tb_tiles: int = 0, tb_bands: int = 0, threshold: Optional[float] = None,
+                 link_items: int = 0):
         self.ctx = ctx
         self._pairs = _Pairs(pairs)
         self.count = self._pairs.count
@@ -385,7 +386,7 @@ class Batch:
         if threshold is not None:
             flags |= LCS_THRESHOLD
         t = _tuning(words_per_lane, ckpt_interval, persistent_waves, plain, strip_rows, tb_tiles,
-                    tb_bands)
+                    tb_bands, link_items)
         h = ctypes.c_void_p()
         _check(_lib.lcs_batch_create(ctx.h, self._pairs.ptr(), self.count,
                                      ctypes.byref(self._alpha.c), flags, ctypes.byref(t),

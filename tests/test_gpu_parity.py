@@ -413,3 +413,42 @@ def test_long_related_pair_scaled_exact(ctx, lcs):
     _say("long related pair 40000 exact")
     assert lcs.lcs_length(ctx, x, y, "dna") == oracle.lcs_length(x, y)
     assert lcs.lcs_traceback(ctx, x, y, "dna") == oracle.lcs_traceback_ckpt(x, y, 1024)
+
+
+def test_chains_starting_in_shared_items(ctx, lcs):
+    # long pairs whose chains start in the free lanes of the item before
+    # them (link_items > 1): lengths and strings exact, lengths-only and
+    # threshold passes too
+    g = inputs.rng(8400)
+    pairs = []
+    for k in range(14):
+        m = int(g.integers(9000, 9400))
+        x = _rand(g, m, inputs.DNA)
+        y, _ = inputs.mutate(g, x, float(g.uniform(0.05, 0.25)), inputs.DNA)
+        pairs.append((x.tobytes(), y.tobytes()))
+    pairs += [(_rand(g, 300, inputs.DNA).tobytes(), _rand(g, 9100, inputs.DNA).tobytes())]
+    want_s = _oracle_tracebacks(pairs)
+    want_l = np.array([len(s) for s in want_s], dtype=np.uint64)
+    d = lcs.plan_describe([len(x) for x, _ in pairs], [len(y) for _, y in pairs], 4,
+                          traceback=True, words_per_lane=1, link_items=32)
+    d1 = lcs.plan_describe([len(x) for x, _ in pairs], [len(y) for _, y in pairs], 4,
+                           traceback=True, words_per_lane=1, link_items=1)
+    assert d["groups"] < d1["groups"]       # some chains do share an item
+    _say("shared-item chains, traceback")
+    with lcs.Batch(ctx, pairs, "dna", traceback=True, words_per_lane=1, link_items=32) as b:
+        b.run()
+        assert b.tracebacks() == want_s
+        assert np.array_equal(b.lengths(), want_l)
+    _say("shared-item chains, lengths and threshold")
+    with lcs.Batch(ctx, pairs, "dna", words_per_lane=1, link_items=32) as b:
+        b.run()
+        assert np.array_equal(b.lengths(), want_l)
+    m = np.array([len(x) for x, _ in pairs], dtype=np.float64)
+    sim = (100.0 * want_l.astype(np.float64)) / m
+    for pct in (70.0, 85.0, 95.0):
+        with lcs.Batch(ctx, pairs, "dna", words_per_lane=1, link_items=32, threshold=pct) as b:
+            b.run()
+            ok, lens = b.decisions()
+            assert np.array_equal(ok, sim >= pct)
+            known = lens != lcs.LCS_LENGTH_UNKNOWN
+            assert np.array_equal(lens[known], want_l[known])
