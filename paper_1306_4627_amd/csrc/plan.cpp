@@ -56,18 +56,26 @@ int max_wpl(int sigma) {
     return wpl_fits(sigma, 1) ? 1 : 0;
 }
 
-// One words-per-lane for the whole batch (one fill launch): two words per
-// lane once most of the cells belong to pairs longer than 16 words (the
-// per-step overhead is then spread over 128 rows), one word otherwise
-// (short columns keep more lanes busy).
+// One words-per-lane for the whole batch (one fill launch).  When every
+// lane of the batch at one word per lane fits the GPU's resident wave slots
+// at once (256 CUs x 16 waves x 64 lanes), the fill is bound by the latency
+// of a step, which grows with the words in a lane's carry chain: one word
+// (a single 262144-row pair: 12.0 ms against 15.0 at two words).
+// Otherwise two words per lane once most of the cells belong to pairs
+// longer than 16 words (the per-step overhead is then spread over 128
+// rows), one word otherwise (short columns keep more lanes busy).
+constexpr uint64_t kResidentLanes = 256ull * 16 * 64;
+
 static int auto_batch_wpl(const std::vector<PairShape> &pairs, int sigma) {
     double big = 0, all = 0;
+    uint64_t lanes1 = 0;
     for (const PairShape &p : pairs) {
         const double c = (double)p.m * (double)p.n;
         all += c;
         if ((p.m + 63) / 64 > 16) big += c;
+        if (p.n) lanes1 += (p.m + 63) / 64;
     }
-    int w = (all > 0 && big >= 0.5 * all) ? 2 : 1;
+    int w = (all > 0 && big >= 0.5 * all && lanes1 > kResidentLanes) ? 2 : 1;
     int mw = max_wpl(sigma);
     return w < mw ? w : mw;
 }
