@@ -43,12 +43,15 @@ __device__ __forceinline__ void load16(const uint16_t *ys, uint32_t t0, uint32_t
 // item: one scalar add-with-carry chain shifts the mask (2 * mask, the carry
 // into the low word being the next step's hand-over bit, selected by
 // s_bitcmp1 from `innext`, bit s = the bit of step s+1) and lane 63's carry
-// (bit 63 of the mask) is shifted into `ow` (most recent step in bit 0): in
-// the traceback fill by the same chain's carry out, elsewhere by plain code
-// the compiler schedules (the forms that measured fastest for each).  With TB, every lane's carry-in bits are accumulated (newest in bit 0:
+// (bit 63 of the mask) is shifted into `ow` (most recent step in bit 0): with
+// OWASM by the same chain's carry out, else by plain code the compiler
+// schedules.  Which is faster depends on the mode and width (the plain form
+// leaves the lengths-only fill many SGPRs to spill into VGPR lanes, which at
+// two words per lane it still hides, at one word per lane and in the other
+// modes not), so the kernel picks per instantiation.  With TB, every lane's carry-in bits are accumulated (newest in bit 0:
 // acc = 2 * acc + carry-in, one v_addc_co_u32 with the mask as carry-in) and
 // stored every 32 steps.
-template <int WPL, bool TB, bool CHAIN, bool RAW>
+template <int WPL, bool TB, bool CHAIN, bool RAW, bool OWASM>
 __device__ __forceinline__ void run16(const uint32_t (&Yg)[8], uint32_t t, const char *lanecol,
                                       uint64_t notstart, uint64_t &cmask, uint32_t &acc,
                                       uint32_t *cbp, uint32_t (&vlo)[WPL], uint32_t (&vhi)[WPL],
@@ -80,7 +83,7 @@ __device__ __forceinline__ void run16(const uint32_t (&Yg)[8], uint32_t t, const
             if (CHAIN) {
                 const uint32_t clo = (uint32_t)cm, chi = (uint32_t)(cm >> 32);
                 uint32_t lo, hi;
-                if (TB) {
+                if (OWASM) {
                     asm("s_bitcmp1_b32 %[in], %[bit]\n\t"
                         "s_addc_u32 %[lo], %[clo], %[clo]\n\t"
                         "s_addc_u32 %[hi], %[chi], %[chi]\n\t"
@@ -168,6 +171,13 @@ template <int WPL, int MODE, bool RAW>
 __device__ __forceinline__ void fill_body(const FillArgs &a) {
     constexpr bool TB = MODE == kFillTraceback;
     constexpr bool THR = MODE == kFillThreshold;
+    // lane 63's carries collected in the scalar chain itself, except in the
+    // lengths-only fill at two or more words per lane (interleaved timings:
+    // 4096-pair related batch, lengths only at two words: 5.82 ms plain vs
+    // 6.63 ms; threshold pass at two words: 5.86 vs 5.07 ms; 65536 short
+    // pairs at one word: 0.229 vs 0.217 ms; one long pair at one word: 47.6
+    // vs 44.2 ns per step)
+    constexpr bool OWASM = TB || THR || WPL == 1;
     extern __shared__ uint64_t smem[];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -393,13 +403,13 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
                 // is the bit of step (group start + s + 1) of the chunk
                 uint32_t ow_lo = 0, ow_hi = 0;
                 load16(ys, t + 32, Y2);
-                run16<WPL, TB, true, RAW>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
+                run16<WPL, TB, true, RAW, OWASM>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
                                           (uint32_t)(inbits >> 1), ow_lo);
                 load16(ys, t + 48, Y3);
-                run16<WPL, TB, true, RAW>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
+                run16<WPL, TB, true, RAW, OWASM>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
                                           (uint32_t)(inbits >> 17), ow_lo);
                 load16(ys, t + 64, Y0);
-                run16<WPL, TB, true, RAW>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
+                run16<WPL, TB, true, RAW, OWASM>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
                                           (uint32_t)(inbits >> 33), ow_hi);
                 load16(ys, t + 80, Y1);
                 if (live_in) {
@@ -410,7 +420,7 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
                         pw2 = __hip_atomic_load(xs_in + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
                 if (THR) pdec_nx = load_state(a.thr_dec, pair);
-                run16<WPL, TB, true, RAW>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
+                run16<WPL, TB, true, RAW, OWASM>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
                                           (uint32_t)(inbits >> 49), ow_hi);
                 // lane 63's carries of the chunk, step e in bit e
                 const uint64_t outbits =
@@ -428,14 +438,14 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
             } else {
                 uint32_t dummy_ow = 0;
                 load16(ys, t + 32, Y2);
-                run16<WPL, TB, false, RAW>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
+                run16<WPL, TB, false, RAW, OWASM>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
                 load16(ys, t + 48, Y3);
-                run16<WPL, TB, false, RAW>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
+                run16<WPL, TB, false, RAW, OWASM>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
                 load16(ys, t + 64, Y0);
-                run16<WPL, TB, false, RAW>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
+                run16<WPL, TB, false, RAW, OWASM>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
                 load16(ys, t + 80, Y1);
                 if (THR) pdec_nx = load_state(a.thr_dec, pair);
-                run16<WPL, TB, false, RAW>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
+                run16<WPL, TB, false, RAW, OWASM>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
             }
         }
         if (aborted) {
