@@ -310,7 +310,7 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
         // their instructions first; shorter items fill the remaining slots.
         if (T >= a.prio_T) __builtin_amdgcn_s_setprio(2);
         else __builtin_amdgcn_s_setprio(0);
-        uint64_t pw0 = 0, pw1 = 0, pw2 = 0;   // hand-over words requested one group early
+        uint64_t pw0 = 0, pw1 = 0, pw2 = 0;   // hand-over words requested one chunk early
 
         for (uint32_t c = 0; c < nch; ++c) {
             uint64_t inbits = 0;
@@ -393,6 +393,18 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
                 // the chained pair at lane 0 answered: stop waiting for it
                 if (live_in && __builtin_amdgcn_readlane(pdec, 0) != 0) live_in = false;
             }
+            // The hand-over words of this chunk (used at the start of the next
+            // one) and the pair states are requested now, a whole chunk ahead:
+            // a device-scope load takes about as long as a chunk of a wave
+            // that has its SIMD to itself, so a later request would stall the
+            // next chunk's start.  Words not yet written are polled again.
+            if (live_in) {
+                pw0 = __hip_atomic_load(xf_in + 2 * c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                pw1 = __hip_atomic_load(xf_in + 2 * c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (THR && (c + 1 + kThrEvery - phase) % kThrEvery == 0)
+                    pw2 = __hip_atomic_load(xs_in + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (THR) pdec_nx = load_state(a.thr_dec, pair);
             if (TB && ((c * 64u) % (uint32_t)a.ckpt_every) == 0) {
                 uint64_t *dst = ckp + (size_t)((c * 64u) / (uint32_t)a.ckpt_every) * RS;
 #pragma unroll
@@ -412,14 +424,6 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
                 run16<WPL, TB, true, RAW, OWASM>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
                                           (uint32_t)(inbits >> 33), ow_hi);
                 load16(ys, t + 80, Y1);
-                if (live_in) {
-                    pw0 = __hip_atomic_load(xf_in + 2 * c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    pw1 = __hip_atomic_load(xf_in + 2 * c + 1, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-                    if (THR && (c + 1 + kThrEvery - phase) % kThrEvery == 0)
-                        pw2 = __hip_atomic_load(xs_in + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                if (THR) pdec_nx = load_state(a.thr_dec, pair);
                 run16<WPL, TB, true, RAW, OWASM>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
                                           (uint32_t)(inbits >> 49), ow_hi);
                 // lane 63's carries of the chunk, step e in bit e
@@ -444,7 +448,6 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
                 load16(ys, t + 64, Y0);
                 run16<WPL, TB, false, RAW, OWASM>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
                 load16(ys, t + 80, Y1);
-                if (THR) pdec_nx = load_state(a.thr_dec, pair);
                 run16<WPL, TB, false, RAW, OWASM>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
             }
         }
