@@ -294,6 +294,11 @@ def main() -> int:
         fill_ms.append(f)
     fill_avg = float(np.mean(fill_ms))
     achieved = cells / (fill_avg * 1e-3) / 1e12
+    # shader clock measured during the last eager fill (first wave's span)
+    try:
+        clock_mhz = batch.clock_mhz()
+    except lcs.LcsError:
+        clock_mhz = None
     log(f"step {ms_per_step:.3f} ms (graph events {np.mean(total_ms):.3f} ms, eager {np.mean(eager_ms):.3f} ms), "
         f"fill {fill_avg:.3f} ms")
     # correctness spot check against the lengths of the first run
@@ -310,6 +315,11 @@ def main() -> int:
                      "traffic": measured_traffic(config["workload"], info["words_per_lane"],
                                                  info["ckpt_interval"]),
                      "kernel": "k_fill", "fill_ms": round(fill_avg, 4),
+                     "clock_mhz_measured": None if clock_mhz is None else round(clock_mhz, 1),
+                     "peak_at_measured_clock": None if clock_mhz is None
+                     else round(PEAK_TCUPS * clock_mhz / 2400.0, 1),
+                     "frac_at_measured_clock": None if clock_mhz is None
+                     else round(achieved / (PEAK_TCUPS * clock_mhz / 2400.0), 4),
                      "eager_pass_ms": round(float(np.mean(eager_ms)), 4)},
         "plan": {k: info[k] for k in ("groups", "lanes", "lane_steps", "words_per_lane",
                                       "ckpt_interval", "classes", "device_bytes")},

@@ -230,6 +230,13 @@ lcs_status lcs_batch_info(const lcs_batch *batch, lcs_batch_stats *out);
  * alone, or -1 for a graph replay; either pointer may be NULL. */
 lcs_status lcs_batch_time(lcs_batch *batch, int eager, float *total_ms, float *fill_ms);
 
+/* Shader clock during the batch's last fill launch, in MHz: the shader-cycle
+ * counter over the 100 MHz counter, both read by the fill's first wave when
+ * it starts and when it finds no more work (so: the clock while the fill
+ * ran at full load).  LCS_ERR_ARG before the first run; LCS_ERR_DEVICE if
+ * the counters did not advance. */
+lcs_status lcs_batch_clock(lcs_batch *batch, double *mhz);
+
 /* Release a batch (NULL is ignored). */
 void lcs_batch_destroy(lcs_batch *batch);
 

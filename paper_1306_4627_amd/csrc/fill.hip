@@ -189,12 +189,25 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
     // threshold pass: 64 segment sums and 64 segment answers per wave
     uint32_t *tslot = nullptr;
     if (THR) tslot = (uint32_t *)(smem + (size_t)(blockDim.x >> 6) * sig1 * RS) + wv * 128;
+    // the clock during the fill: shader cycles over 100 MHz ticks of the
+    // first wave's lifetime
+    const bool clk_lane = a.clk && blockIdx.x == 0 && threadIdx.x == 0;
+    if (clk_lane) {
+        a.clk[0] = __builtin_amdgcn_s_memtime();
+        a.clk[1] = __builtin_amdgcn_s_memrealtime();
+    }
 
     for (;;) {
         uint32_t ticket = 0;
         if (lane == 0) ticket = atomicAdd(a.queue, 1u);
         ticket = __builtin_amdgcn_readfirstlane(ticket);
-        if (ticket >= a.item_end - a.item_begin) return;
+        if (ticket >= a.item_end - a.item_begin) {
+            if (clk_lane) {
+                a.clk[2] = __builtin_amdgcn_s_memtime();
+                a.clk[3] = __builtin_amdgcn_s_memrealtime();
+            }
+            return;
+        }
         const uint32_t item = a.item_begin + ticket;
 
         const size_t li = (size_t)item * 64 + lane;

@@ -72,6 +72,9 @@ struct FillArgs {
     uint32_t *thr_dec;         // 0 open, 1 reaches its target, 2 cannot
     uint64_t *xsum;            // running zero counts handed up a chain: one
                                // tagged word per chunk per feeder (zeroed)
+    // optional: the shader-clock and 100 MHz counters read by the first wave
+    // of work-group 0 when it starts and when it finds the queue empty
+    uint64_t *clk;
 };
 
 // What a fill launch computes: lengths only, lengths plus the checkpoints the

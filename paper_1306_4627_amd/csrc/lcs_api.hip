@@ -141,6 +141,7 @@ struct lcs_batch {
     uint64_t *zero64 = nullptr;
     uint64_t nzero64 = 0;
     uint32_t *error = nullptr;
+    uint64_t *clk = nullptr;       // clock counters of the last fill launch
     // threshold pass: per-pair target length (host copy and device) and
     // answer word (0 open, 1 reaches the target, 2 cannot; read back with the
     // lengths)
@@ -455,6 +456,7 @@ static size_t carve(lcs_batch *b, char *base) {
     b->out = cv.take<uint8_t>(b->out_bytes + 64);
     b->readback_bytes = (size_t)((char *)(b->out + b->out_bytes) - (char *)b->out_len);
     // ---- device only ----
+    b->clk = cv.take<uint64_t>(4);
     b->xcodes = cv.take<uint8_t>(b->xarena + 64);
     b->ystream = cv.take<uint16_t>(p.ys_elems + 64);
     // zeroed before every pass, 64-bit: traceback bitmaps, then the carry
@@ -844,6 +846,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         fa.spin_limit = b->spin_limit;
         fa.sigma = b->sigma;
         fa.ckpt_every = b->ckpt;
+        fa.clk = b->clk;
         if (mode == kFillThreshold) {
             fa.pair_n = b->pair_n;
             fa.thr_t = b->thr_t;
@@ -1190,6 +1193,19 @@ extern "C" lcs_status lcs_batch_time(lcs_batch *b, int eager, float *total_ms, f
             *fill_ms = -1.f;
         }
     }
+    return LCS_OK;
+}
+
+extern "C" lcs_status lcs_batch_clock(lcs_batch *b, double *mhz) {
+    if (!b || !mhz || !b->ran) return LCS_ERR_ARG;
+    lcs_ctx *ctx = b->ctx;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
+    HIP_TRY(hipStreamSynchronize(b->hooks.stream ? b->hooks.stream : ctx->stream));
+    uint64_t c[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpy(c, b->clk, sizeof c, hipMemcpyDeviceToHost));
+    if (c[3] <= c[1] || c[2] <= c[0]) return LCS_ERR_DEVICE;
+    // shader cycles per tick of the 100 MHz counter
+    *mhz = 100.0 * (double)(c[2] - c[0]) / (double)(c[3] - c[1]);
     return LCS_OK;
 }
 

@@ -155,6 +155,8 @@ def _load() -> ctypes.CDLL:
     lib.lcs_batch_set_threshold.restype = i32
     lib.lcs_batch_decisions.argtypes = [vp, u8p, u64p]
     lib.lcs_batch_decisions.restype = i32
+    lib.lcs_batch_clock.argtypes = [vp, P(ctypes.c_double)]
+    lib.lcs_batch_clock.restype = i32
     lib.lcs_server_create.argtypes = [vp, P(lcs_server_config), P(vp)]
     lib.lcs_server_create.restype = i32
     lib.lcs_server_destroy.argtypes = [vp]
@@ -427,6 +429,12 @@ class Batch:
                                          lens.ctypes.data_as(P64)), "lcs_batch_tracebacks")
         return [arena[int(o):int(o) + int(l)].tobytes()
                 for o, l in zip(offs[:self.count], lens[:self.count])]
+
+    def clock_mhz(self) -> float:
+        """Shader clock (MHz) measured during the last fill launch."""
+        v = ctypes.c_double()
+        _check(_lib.lcs_batch_clock(self.h, ctypes.byref(v)), "lcs_batch_clock")
+        return float(v.value)
 
     def info(self) -> dict:
         s = lcs_batch_stats()

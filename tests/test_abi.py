@@ -79,6 +79,8 @@ def test_threshold_arguments_and_flags_rejected_before_any_device_call():
     assert L.lcs_similarity_batch(None, None, 0, ctypes.byref(al), pct) == lcs.LCS_ERR_ARG
     assert L.lcs_batch_set_threshold(None, 50.0) == lcs.LCS_ERR_ARG
     assert L.lcs_batch_decisions(None, ok, n) == lcs.LCS_ERR_ARG
+    mhz = ctypes.c_double()
+    assert L.lcs_batch_clock(None, ctypes.byref(mhz)) == lcs.LCS_ERR_ARG
     # the threshold pass plans like a lengths-only pass; never with a traceback
     m = np.array([100, 9000], dtype=np.uint64)
     P64 = ctypes.POINTER(ctypes.c_uint64)

@@ -452,3 +452,17 @@ def test_chains_starting_in_shared_items(ctx, lcs):
             assert np.array_equal(ok, sim >= pct)
             known = lens != lcs.LCS_LENGTH_UNKNOWN
             assert np.array_equal(lens[known], want_l[known])
+
+
+def test_fill_clock_is_measured(ctx, lcs):
+    # the shader clock read by the fill's first wave over its lifetime
+    g = inputs.rng(8500)
+    pairs = [(_rand(g, 20000, inputs.DNA).tobytes(), _rand(g, 20000, inputs.DNA).tobytes())
+             for _ in range(64)]
+    _say("fill clock")
+    with lcs.Batch(ctx, pairs, "dna") as b:
+        with pytest.raises(lcs.LcsError):
+            b.clock_mhz()                     # not run yet
+        b.time(eager=True)
+        mhz = b.clock_mhz()
+    assert 300.0 < mhz < 3000.0, mhz
