@@ -59,6 +59,9 @@ struct Request {
     bool same_group(const Request &o) const {
         return tb == o.tb && alpha_size == o.alpha_size && symbols == o.symbols;
     }
+    // small enough for the express stream
+    bool small() const { return (uint64_t)x.size() * (uint64_t)y.size() <= kExpressCells; }
+    static constexpr uint64_t kExpressCells = 1ull << 24;
 };
 
 // First-fit allocator over one device allocation.
@@ -165,6 +168,11 @@ void lcs_server::run() {
     for (int k = nstreams - 1; k >= 0; --k) free_streams.push_back(k);
     uint32_t group_limit = max_batch;
     bool wait_completion = false;   // a lone request waits for memory to come back
+    // With two or more streams, stream 0 is an express stream: it only takes
+    // batches of small requests (at most 2^24 cells each), so that a burst
+    // of long requests occupying the other streams does not hold up the many
+    // short ones behind it.
+    const int express = nstreams >= 2 ? 0 : -1;
     for (;;) {
         // ---- finished batches ----
         for (size_t f = 0; f < flights.size();) {
@@ -214,11 +222,31 @@ void lcs_server::run() {
         }
         // ---- admission ----
         std::vector<Request *> group;
+        int si = -1;
         {
             std::unique_lock<std::mutex> lk(mu);
             if (stop && pending.empty() && flights.empty()) break;
-            const bool can_admit = !pending.empty() && !free_streams.empty() && !wait_completion;
-            if (!can_admit) {
+            // a free general stream, else the express stream for small ones
+            bool express_only = false;
+            for (int k : free_streams)
+                if (k != express) si = k;
+            if (si < 0 && !free_streams.empty()) {
+                si = express;
+                express_only = true;
+            }
+            Request *head = nullptr;
+            if (!pending.empty() && si >= 0 && !wait_completion) {
+                if (!express_only) {
+                    head = pending.front();
+                } else {
+                    for (Request *r : pending)
+                        if (r->small()) {
+                            head = r;
+                            break;
+                        }
+                }
+            }
+            if (!head) {
                 if (flights.empty()) {
                     cv_work.wait(lk, [&] { return stop || !pending.empty(); });
                 } else {
@@ -227,10 +255,10 @@ void lcs_server::run() {
                 }
                 continue;
             }
-            // the oldest request and the following ones of its group
-            Request *head = pending.front();
+            // the oldest (small, on the express stream) request and the
+            // following ones of its group
             for (auto it = pending.begin(); it != pending.end() && group.size() < group_limit;) {
-                if ((*it)->same_group(*head)) {
+                if ((*it)->same_group(*head) && (!express_only || (*it)->small())) {
                     group.push_back(*it);
                     it = pending.erase(it);
                 } else {
@@ -252,7 +280,6 @@ void lcs_server::run() {
         const Request &h = *group[0];
         const lcs_alphabet al{h.alpha_size, h.symbols.empty() ? nullptr : h.symbols.data()};
         const uint32_t flags = h.tb ? LCS_WANT_TRACEBACK : 0u;
-        const int si = free_streams.back();
         lcs::BatchHooks hooks;
         hooks.stream = streams[si];
         hooks.alloc = arena_alloc;
@@ -294,7 +321,7 @@ void lcs_server::run() {
             cv_done.notify_all();
             continue;
         }
-        free_streams.pop_back();
+        free_streams.erase(std::find(free_streams.begin(), free_streams.end(), si));
         const uint64_t t_launched = now_ns();
         {
             std::lock_guard<std::mutex> lk(mu);
