@@ -225,6 +225,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server leg")
     ap.add_argument("--no-threshold", action="store_true", help="skip the threshold-pass leg")
+    ap.add_argument("--no-schedule", action="store_true",
+                    help="skip the traced fill pass (per-item schedule summary)")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-only", action="store_true",
                     help="only run the request-server leg and print its results")
@@ -337,6 +339,22 @@ def main() -> int:
         out["plain_per_pair"] = {"value": round(cells / (t_plain * 1e-3) / 1e9, 2), "unit": "GCUPS",
                                  "ms": round(t_plain, 3)}
         out["batched_over_plain"] = round(value / out["plain_per_pair"]["value"], 2)
+    if not args.no_schedule:
+        # one more eager pass of the same plan with per-item schedule records
+        # (outside the timed runs above)
+        log("fill schedule leg")
+        from paper_1306_4627_amd import fill_schedule
+        with lcs.Batch(ctx, pairs, alpha, traceback=tb, fill_trace=True, **tuning) as sb:
+            sb.time(eager=True)
+            _, f_tr = sb.time(eager=True)
+            sm = fill_schedule.summarize(sb.fill_trace())
+            same = np.array_equal(sb.lengths(), lens)
+        out["fill_schedule"] = {"traced_fill_ms": round(f_tr, 4),
+                                **{k: round(v, 4) if isinstance(v, float) else v
+                                   for k, v in sm.items()}}
+        if not same:
+            log("traced and untraced lengths differ!")
+            out["fill_schedule"]["lengths_mismatch"] = True
     if not args.no_threshold:
         log("threshold-pass leg")
         out["threshold"] = threshold_leg(lcs, ctx, pairs, alpha)

@@ -84,6 +84,8 @@ typedef struct lcs_batch lcs_batch;
 #define LCS_USE_GRAPH      2u   /* replay the launch sequence as a HIP graph */
 #define LCS_THRESHOLD      4u   /* threshold pass (lcs_batch_set_threshold); not
                                    with LCS_WANT_TRACEBACK */
+#define LCS_FILL_TRACE     8u   /* record when every fill work item ran
+                                   (lcs_batch_fill_trace) */
 
 /* Length reported for a pair whose threshold answer came before its last
  * column (the fill of that pair stopped early). */
@@ -198,8 +200,8 @@ lcs_status lcs_traceback_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t cou
 
 /* Plan and upload a batch without running it.  The input bytes are copied to
  * device memory; the caller's host buffers may be released afterwards.
- * flags: LCS_WANT_TRACEBACK | LCS_USE_GRAPH | LCS_THRESHOLD.  tuning may be
- * NULL (automatic).
+ * flags: LCS_WANT_TRACEBACK | LCS_USE_GRAPH | LCS_THRESHOLD | LCS_FILL_TRACE.
+ * tuning may be NULL (automatic).
  * Fails with LCS_ERR_NOMEM when the batch would exceed the context budget. */
 lcs_status lcs_batch_create(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
                             const lcs_alphabet *alphabet, uint32_t flags,
@@ -236,6 +238,34 @@ lcs_status lcs_batch_time(lcs_batch *batch, int eager, float *total_ms, float *f
  * ran at full load).  LCS_ERR_ARG before the first run; LCS_ERR_DEVICE if
  * the counters did not advance. */
 lcs_status lcs_batch_clock(lcs_batch *batch, double *mhz);
+
+/* Schedule record of one fill work item (64 lanes' share of the column
+ * steps, run by one wavefront from the persistent queue) in the last pass of a
+ * batch created with LCS_FILL_TRACE.  Times are nanoseconds after the earliest
+ * item of the pass was taken, from the GPU's 100 MHz counter (10 ns
+ * resolution). */
+typedef struct {
+    uint64_t start_ns;       /* taken from the queue */
+    uint64_t first_step_ns;  /* match masks built; first column step */
+    uint64_t end_ns;         /* after the last column step */
+    uint64_t wait_ns;        /* spent waiting for the carries of its feeder */
+    uint32_t steps;          /* column steps of the item */
+    int32_t feeder;          /* index of the item that hands it carries, -1 if none */
+    uint32_t feeds;          /* 1 when it hands carries to the next item */
+    uint32_t ran;            /* 0 when the pass never took it (a failed pass) */
+    uint32_t hw_id;          /* HW_ID of the wavefront that ran it: wave slot
+                                (bits 0-3), SIMD (4-5), CU (8-11), shader array
+                                (12), shader engine (13-15) */
+    uint32_t xcc_id;         /* XCC_ID: the accelerator die (bits 0-3) */
+} lcs_fill_item;
+
+/* Schedule records of the batch's last pass, one per fill work item in queue
+ * order (all classes).  *count receives the number of items; with out NULL
+ * only the count is returned.  LCS_ERR_ARG if the batch was created without
+ * LCS_FILL_TRACE, before its first run, or if cap < *count.  The records cost
+ * the fill a few stores per item; keep the flag off for timed runs. */
+lcs_status lcs_batch_fill_trace(lcs_batch *batch, lcs_fill_item *out, uint64_t cap,
+                                uint64_t *count);
 
 /* Release a batch (NULL is ignored). */
 void lcs_batch_destroy(lcs_batch *batch);

@@ -209,6 +209,7 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
             return;
         }
         const uint32_t item = a.item_begin + ticket;
+        const uint64_t taken = a.trace ? __builtin_amdgcn_s_memrealtime() : 0;
 
         const size_t li = (size_t)item * 64 + lane;
         const int32_t pair = a.ln_pair[li];
@@ -265,6 +266,10 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
         }
 
         // ---- column steps ----
+        if (a.trace && lane == 0) {
+            a.trace[(size_t)item * kTraceWords] = taken;
+            a.trace[(size_t)item * kTraceWords + 1] = __builtin_amdgcn_s_memrealtime();
+        }
         uint32_t vlo[WPL], vhi[WPL];
 #pragma unroll
         for (int q = 0; q < WPL; ++q) { vlo[q] = ~0u; vhi[q] = ~0u; }
@@ -324,6 +329,7 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
         if (T >= a.prio_T) __builtin_amdgcn_s_setprio(2);
         else __builtin_amdgcn_s_setprio(0);
         uint64_t pw0 = 0, pw1 = 0, pw2 = 0;   // hand-over words requested one chunk early
+        uint64_t waited = 0;                   // schedule record: ticks spent waiting
 
         for (uint32_t c = 0; c < nch; ++c) {
             uint64_t inbits = 0;
@@ -333,6 +339,9 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
                 uint32_t spins = 0;
                 // (the running sum is handed up only for this item's check chunks)
                 const bool want_sum = THR && (c + kThrEvery - phase) % kThrEvery == 0;
+                const bool late = (uint32_t)(w0 >> 32) != c || (uint32_t)(w1 >> 32) != c ||
+                                  (want_sum && (uint32_t)(w2 >> 32) != c);
+                const uint64_t wait0 = (a.trace && late) ? __builtin_amdgcn_s_memrealtime() : 0;
                 while ((uint32_t)(w0 >> 32) != c || (uint32_t)(w1 >> 32) != c ||
                        (want_sum && (uint32_t)(w2 >> 32) != c)) {
                     // bounded wait for the feeding item to finish chunk c-1
@@ -353,6 +362,7 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
                         w2 = uniform64(__hip_atomic_load(xs_in + (c - 1), __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT));
                 }
+                if (wait0) waited += __builtin_amdgcn_s_memrealtime() - wait0;
                 if (aborted || stopped) break;
                 inbits = (w1 << 32) | (w0 & 0xffffffffull);
                 hin = (uint32_t)w2;
@@ -463,6 +473,14 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
                 load16(ys, t + 80, Y1);
                 run16<WPL, TB, false, RAW, OWASM>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
             }
+        }
+        if (a.trace && lane == 0) {
+            uint64_t *r = a.trace + (size_t)item * kTraceWords;
+            r[2] = __builtin_amdgcn_s_memrealtime();
+            r[3] = waited;
+            // HW_ID and XCC_ID, all 32 bits of each
+            r[4] = ((uint64_t)__builtin_amdgcn_s_getreg((31 << 11) | 4) << 32) |
+                   __builtin_amdgcn_s_getreg((31 << 11) | 20);
         }
         if (aborted) {
             if (lane == 0) atomicOr(a.error, 1u);

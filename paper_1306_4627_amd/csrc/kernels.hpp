@@ -75,7 +75,15 @@ struct FillArgs {
     // optional: the shader-clock and 100 MHz counters read by the first wave
     // of work-group 0 when it starts and when it finds the queue empty
     uint64_t *clk;
+    // optional schedule record of every item (kTraceWords words, zeroed
+    // before the pass): 100 MHz counter when the item is taken from the
+    // queue, at its first column step and after its last one; counter ticks
+    // spent waiting for the feeding item's carries; HW_ID (high half) and
+    // XCC_ID (low half) of the wave that ran it
+    uint64_t *trace;
 };
+
+constexpr int kTraceWords = 6;
 
 // What a fill launch computes: lengths only, lengths plus the checkpoints the
 // traceback reads, or the threshold pass (lengths of the pairs it does not

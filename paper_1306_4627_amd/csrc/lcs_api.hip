@@ -71,6 +71,7 @@ struct ClassDev {
     uint32_t *cbits = nullptr;
     uint64_t *xfer = nullptr;
     uint64_t *xsum = nullptr;          // threshold pass: running sums handed up chains
+    uint64_t *trace = nullptr;         // schedule records of the fill items (LCS_FILL_TRACE)
     uint32_t *plain_ctr = nullptr;     // plain mode: kQueues queue counters per pair
     uint32_t *q_fill = nullptr, *q_spec = nullptr, *q_fix = nullptr, *q_seal = nullptr;
     uint32_t fill_grid = 1, sp_grid = 1, fx_grid = 1, sl_grid = 1;
@@ -462,7 +463,9 @@ static size_t carve(lcs_batch *b, char *base) {
     // zeroed before every pass, 64-bit: traceback bitmaps, then the carry
     // hand-over words of every class
     uint64_t nz64 = (b->flags & LCS_WANT_TRACEBACK) ? b->diag_words : 0;
-    for (const ClassPlan &C : p.classes) nz64 += C.xf_words + (thr ? C.xf_words / 2 : 0);
+    const bool traced = (b->flags & LCS_FILL_TRACE) != 0;
+    for (const ClassPlan &C : p.classes)
+        nz64 += C.xf_words + (thr ? C.xf_words / 2 : 0) + (traced ? C.it_T.size() * kTraceWords : 0);
     b->zero64 = cv.take<uint64_t>(nz64 + 1);
     b->nzero64 = nz64;
     b->diag = b->zero64;
@@ -480,6 +483,10 @@ static size_t carve(lcs_batch *b, char *base) {
         if (thr) {
             D.xsum = b->zero64 ? b->zero64 + z64 : nullptr;
             z64 += C.xf_words / 2;
+        }
+        if (traced) {
+            D.trace = b->zero64 ? b->zero64 + z64 : nullptr;
+            z64 += C.it_T.size() * kTraceWords;
         }
         D.q_fill = b->zero ? b->zero + zc : nullptr;
         D.q_spec = b->zero ? b->zero + zc + 1 : nullptr;
@@ -519,7 +526,8 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
                               const lcs_tuning *tuning, lcs_batch **out,
                               const BatchHooks *hooks = nullptr) {
     if (!ctx || !out) return LCS_ERR_ARG;
-    if (flags & ~(uint32_t)(LCS_WANT_TRACEBACK | LCS_USE_GRAPH | LCS_THRESHOLD)) return LCS_ERR_ARG;
+    if (flags & ~(uint32_t)(LCS_WANT_TRACEBACK | LCS_USE_GRAPH | LCS_THRESHOLD | LCS_FILL_TRACE))
+        return LCS_ERR_ARG;
     if ((flags & LCS_THRESHOLD) && (flags & LCS_WANT_TRACEBACK)) return LCS_ERR_ARG;
     lcs_status st = check_pairs(pairs, count);
     if (st) return st;
@@ -847,6 +855,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         fa.sigma = b->sigma;
         fa.ckpt_every = b->ckpt;
         fa.clk = b->clk;
+        fa.trace = D.trace;
         if (mode == kFillThreshold) {
             fa.pair_n = b->pair_n;
             fa.thr_t = b->thr_t;
@@ -1209,6 +1218,52 @@ extern "C" lcs_status lcs_batch_clock(lcs_batch *b, double *mhz) {
     return LCS_OK;
 }
 
+extern "C" lcs_status lcs_batch_fill_trace(lcs_batch *b, lcs_fill_item *out, uint64_t cap,
+                                           uint64_t *count) {
+    if (!b || !count || !(b->flags & LCS_FILL_TRACE)) return LCS_ERR_ARG;
+    uint64_t total = 0;
+    for (const ClassDev &D : b->cls) total += D.nitems;
+    *count = total;
+    if (!out) return LCS_OK;
+    if (cap < total || !b->ran) return LCS_ERR_ARG;
+    lcs_ctx *ctx = b->ctx;
+    if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
+    HIP_TRY(hipStreamSynchronize(b->hooks.stream ? b->hooks.stream : ctx->stream));
+    std::vector<uint64_t> raw(total * kTraceWords + 1);
+    uint64_t at = 0;
+    for (const ClassDev &D : b->cls) {
+        if (D.nitems)
+            HIP_TRY(hipMemcpy(raw.data() + at * kTraceWords, D.trace,
+                              (size_t)D.nitems * kTraceWords * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        at += D.nitems;
+    }
+    // times relative to the earliest item taken, 100 MHz counter ticks to ns
+    uint64_t t0 = UINT64_MAX;
+    for (uint64_t k = 0; k < total; ++k)
+        if (raw[k * kTraceWords + 2]) t0 = std::min(t0, raw[k * kTraceWords]);
+    const auto ns = [&](uint64_t t) { return t >= t0 ? (t - t0) * 10 : 0; };
+    at = 0;
+    for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+        const ClassPlan &C = b->plan.classes[ci];
+        for (uint64_t i = 0; i < b->cls[ci].nitems; ++i) {
+            const uint64_t *r = raw.data() + (at + i) * kTraceWords;
+            lcs_fill_item &o = out[at + i];
+            o.ran = r[2] != 0;
+            o.start_ns = o.ran ? ns(r[0]) : 0;
+            o.first_step_ns = o.ran ? ns(r[1]) : 0;
+            o.end_ns = o.ran ? ns(r[2]) : 0;
+            o.wait_ns = r[3] * 10;
+            o.steps = C.it_T[i];
+            o.feeder = C.it_prev[i] >= 0 ? (int32_t)(at + (uint64_t)C.it_prev[i]) : -1;
+            o.feeds = C.it_feeds[i] != 0;
+            o.hw_id = (uint32_t)(r[4] >> 32);
+            o.xcc_id = (uint32_t)r[4];
+        }
+        at += b->cls[ci].nitems;
+    }
+    return LCS_OK;
+}
+
 extern "C" void lcs_batch_destroy(lcs_batch *b) { free_batch(b); }
 
 // --------------------------------------------------------------------------
@@ -1521,7 +1576,8 @@ static lcs_status plan_only(const uint64_t *m, const uint64_t *n, uint64_t count
                             std::vector<PairShape> &shapes, Plan &plan) {
     if (count && (!m || !n)) return LCS_ERR_ARG;
     if (alphabet_size < 1 || alphabet_size > 256) return LCS_ERR_ARG;
-    if (flags & ~(uint32_t)(LCS_WANT_TRACEBACK | LCS_USE_GRAPH | LCS_THRESHOLD)) return LCS_ERR_ARG;
+    if (flags & ~(uint32_t)(LCS_WANT_TRACEBACK | LCS_USE_GRAPH | LCS_THRESHOLD | LCS_FILL_TRACE))
+        return LCS_ERR_ARG;
     if ((flags & LCS_THRESHOLD) && (flags & LCS_WANT_TRACEBACK)) return LCS_ERR_ARG;
     lcs_status st = check_tuning(tuning);
     if (st) return st;

@@ -30,7 +30,13 @@ LCS_ERR_UNSUPPORTED = -7
 LCS_WANT_TRACEBACK = 1
 LCS_USE_GRAPH = 2
 LCS_THRESHOLD = 4
+LCS_FILL_TRACE = 8
 LCS_LENGTH_UNKNOWN = (1 << 64) - 1
+
+# lcs_fill_item
+FILL_ITEM = np.dtype([("start_ns", "<u8"), ("first_step_ns", "<u8"), ("end_ns", "<u8"),
+                      ("wait_ns", "<u8"), ("steps", "<u4"), ("feeder", "<i4"), ("feeds", "<u4"),
+                      ("ran", "<u4"), ("hw_id", "<u4"), ("xcc_id", "<u4")])
 
 DNA = b"ACGT"
 PROTEIN = b"ACDEFGHIKLMNPQRSTVWY"
@@ -157,6 +163,8 @@ def _load() -> ctypes.CDLL:
     lib.lcs_batch_decisions.restype = i32
     lib.lcs_batch_clock.argtypes = [vp, P(ctypes.c_double)]
     lib.lcs_batch_clock.restype = i32
+    lib.lcs_batch_fill_trace.argtypes = [vp, vp, u64, u64p]
+    lib.lcs_batch_fill_trace.restype = i32
     lib.lcs_server_create.argtypes = [vp, P(lcs_server_config), P(vp)]
     lib.lcs_server_create.restype = i32
     lib.lcs_server_destroy.argtypes = [vp]
@@ -377,7 +385,7 @@ class Batch:
                  graph: bool = False, words_per_lane: int = 0, ckpt_interval: int = 0,
                  persistent_waves: int = 0, plain: bool = False, strip_rows: int = 0,
                  tb_tiles: int = 0, tb_bands: int = 0, threshold: Optional[float] = None,
-                 link_items: int = 0):
+                 link_items: int = 0, fill_trace: bool = False):
         self.ctx = ctx
         self._pairs = _Pairs(pairs)
         self.count = self._pairs.count
@@ -387,6 +395,8 @@ class Batch:
         flags = (LCS_WANT_TRACEBACK if traceback else 0) | (LCS_USE_GRAPH if graph else 0)
         if threshold is not None:
             flags |= LCS_THRESHOLD
+        if fill_trace:
+            flags |= LCS_FILL_TRACE
         t = _tuning(words_per_lane, ckpt_interval, persistent_waves, plain, strip_rows, tb_tiles,
                     tb_bands, link_items)
         h = ctypes.c_void_p()
@@ -435,6 +445,17 @@ class Batch:
         v = ctypes.c_double()
         _check(_lib.lcs_batch_clock(self.h, ctypes.byref(v)), "lcs_batch_clock")
         return float(v.value)
+
+    def fill_trace(self) -> np.ndarray:
+        """Schedule records of the last pass's fill items (``lcs_batch_fill_trace``;
+        the batch must be created with ``fill_trace=True``), as a structured array
+        with the fields of ``lcs_fill_item``."""
+        n = ctypes.c_uint64()
+        _check(_lib.lcs_batch_fill_trace(self.h, None, 0, ctypes.byref(n)), "lcs_batch_fill_trace")
+        out = np.zeros(max(1, n.value), dtype=FILL_ITEM)
+        _check(_lib.lcs_batch_fill_trace(self.h, out.ctypes.data, n.value, ctypes.byref(n)),
+               "lcs_batch_fill_trace")
+        return out[:n.value]
 
     def info(self) -> dict:
         s = lcs_batch_stats()

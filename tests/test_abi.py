@@ -91,10 +91,19 @@ def test_threshold_arguments_and_flags_rejected_before_any_device_call():
                                ctypes.byref(s)) == lcs.LCS_OK
     assert L.lcs_plan_describe(mp, mp, 2, 4, lcs.LCS_THRESHOLD | lcs.LCS_WANT_TRACEBACK,
                                ctypes.byref(t), ctypes.byref(s)) == lcs.LCS_ERR_ARG
-    assert L.lcs_plan_describe(mp, mp, 2, 4, 8, ctypes.byref(t), ctypes.byref(s)) == lcs.LCS_ERR_ARG
+    assert L.lcs_plan_describe(mp, mp, 2, 4, 16, ctypes.byref(t), ctypes.byref(s)) == lcs.LCS_ERR_ARG
     best = lcs.lcs_tuning()
     assert L.lcs_autotune(None, None, 0, ctypes.byref(al), lcs.LCS_THRESHOLD, ctypes.byref(best),
                           None) == lcs.LCS_ERR_ARG
+    # schedule records plan like the pass they trace; the autotuner does not take them
+    for f in (0, lcs.LCS_WANT_TRACEBACK, lcs.LCS_THRESHOLD):
+        assert L.lcs_plan_describe(mp, mp, 2, 4, f | lcs.LCS_FILL_TRACE, ctypes.byref(t),
+                                   ctypes.byref(s)) == lcs.LCS_OK
+    assert L.lcs_autotune(None, None, 0, ctypes.byref(al), lcs.LCS_FILL_TRACE, ctypes.byref(best),
+                          None) == lcs.LCS_ERR_ARG
+    cnt = ctypes.c_uint64(5)
+    assert L.lcs_batch_fill_trace(None, None, 0, ctypes.byref(cnt)) == lcs.LCS_ERR_ARG
+    assert cnt.value == 5
 
 
 def test_null_arguments_rejected_before_any_device_call():
