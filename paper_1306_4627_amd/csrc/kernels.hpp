@@ -62,7 +62,7 @@ struct FillArgs {
     uint32_t *error;           // set to 1 when a bounded wait runs out
     uint32_t item_begin;
     uint32_t item_end;
-    uint32_t prio_T;           // items with at least this many steps run at raised priority
+    uint32_t prio_half;        // half the longest item's steps: scale of the wave priorities
     uint32_t spin_limit;       // polls before a wait gives up
     int32_t sigma;             // code sigma is the zero-mask sentinel
     int32_t ckpt_every;        // steps between checkpoints (traceback only)

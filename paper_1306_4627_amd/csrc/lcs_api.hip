@@ -78,7 +78,7 @@ struct ClassDev {
     int fill_waves = 4;                // waves per fill work-group
     int nb = 1;                        // traceback tiles per band recomputed together
     int nbands = 1;                    // traceback bands recomputed together
-    uint32_t prio_T = 0xffffffffu;     // fill items this long run at raised priority
+    uint32_t prio_half = 1;            // half the longest fill item's steps (wave priorities)
     // plain mode: one launch per pair and pass
     std::vector<uint32_t> pl_pair;     // pair of each launch
     std::vector<uint32_t> pl_begin, pl_end, pl_tb;  // item range, index in tb list
@@ -716,11 +716,12 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
                                         fill_lds_bytes(C.wpl, sigma, mode), (D.nitems + fw - 1) / fw,
                                         cap > 0 ? (cap + fw - 1) / fw : 0, 64 * fw);
         }
-        // raised priority for the items within half of the longest
+        // the fill's wave priorities are set by the steps an item has left,
+        // at fractions of the longest item
         {
             uint32_t mt = 0;
             for (uint32_t T : C.it_T) mt = std::max(mt, T);
-            D.prio_T = std::max<uint32_t>(mt / 2, 1);
+            D.prio_half = std::max<uint32_t>(mt / 2, 1);
         }
         // traceback recompute rounds: by default tiles spanning about 256
         // columns per band and as many bands (up to four) as fit about 10 KiB
@@ -850,7 +851,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         fa.error = b->error;
         fa.item_begin = 0;
         fa.item_end = D.nitems;
-        fa.prio_T = D.prio_T;
+        fa.prio_half = D.prio_half;
         fa.spin_limit = b->spin_limit;
         fa.sigma = b->sigma;
         fa.ckpt_every = b->ckpt;
