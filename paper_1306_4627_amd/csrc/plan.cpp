@@ -299,6 +299,31 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
                 }
                 if (S >= 2) C.sl_t.push_back((uint32_t)t);
             }
+            // The speculative pass takes its strips longest walk first (rows
+            // plus the columns the straight line from (0, 0) to (m, n) crosses
+            // in the strip), so that no full strip is left to start late.
+            // The strips are independent in this pass.  (Plain mode launches
+            // each pair's strips as one range of tickets: pair order kept.)
+            if (!cfg.plain) {
+                const uint64_t R = (uint64_t)C.strip_bands * band;
+                std::vector<uint64_t> est(C.sp_t.size());
+                for (size_t k = 0; k < est.size(); ++k) {
+                    const PairShape &ps = pairs[C.tb_pair[C.sp_t[k]]];
+                    const uint64_t lo = (uint64_t)C.sp_s[k] * R;
+                    const uint64_t rows = std::min<uint64_t>(R, ps.m - lo);
+                    est[k] = rows + (ps.m ? (uint64_t)((double)ps.n * (double)rows / (double)ps.m) : 0);
+                }
+                std::vector<size_t> o(est.size());
+                std::iota(o.begin(), o.end(), 0);
+                std::stable_sort(o.begin(), o.end(), [&](size_t x, size_t y) { return est[x] > est[y]; });
+                std::vector<uint32_t> st(o.size()), ss(o.size());
+                for (size_t k = 0; k < o.size(); ++k) {
+                    st[k] = C.sp_t[o[k]];
+                    ss[k] = C.sp_s[o[k]];
+                }
+                C.sp_t.swap(st);
+                C.sp_s.swap(ss);
+            }
         }
         out.items += nit;
         out.lanes += nit * kLanes;
@@ -493,6 +518,18 @@ std::string check_plan(const std::vector<PairShape> &pairs, const Plan &p) {
         for (size_t k = 0; k < C.fx_t.size(); ++k) {
             if (C.fx_t[k] >= nt || C.fx_s[k] + 1 >= seen_fx[C.fx_t[k]].size()) return "fix-up ticket range";
             if (seen_fx[C.fx_t[k]][C.fx_s[k]]++) return "strip fixed twice";
+        }
+        if (p.cfg.plain) {
+            // plain mode launches the tickets of one entry in a pass as one range
+            const auto contiguous = [&](const std::vector<uint32_t> &tk) {
+                std::vector<uint8_t> done(nt, 0);
+                for (size_t k = 0; k < tk.size(); ++k) {
+                    if (k > 0 && tk[k] == tk[k - 1]) continue;
+                    if (done[tk[k]]++) return false;
+                }
+                return true;
+            };
+            if (!contiguous(C.sp_t) || !contiguous(C.fx_t)) return "plain tickets not contiguous";
         }
         for (size_t t = 0; t < nt; ++t) {
             for (size_t s = 0; s < seen_sp[t].size(); ++s) {

@@ -178,6 +178,18 @@ def test_packer_plain_mode_one_pair_per_item():
     assert d["groups"] >= 200
 
 
+def test_packer_plain_traceback_tickets_per_pair():
+    # plain mode launches one pair's strips of a pass as one ticket range; the
+    # packed mode orders the speculative strips longest first across pairs
+    g = np.random.default_rng(1)
+    m = g.integers(1, 5000, size=120)
+    n = g.integers(1, 5000, size=120)
+    for wpl in (1, 2):
+        for plain in (True, False):
+            assert lcs.plan_selfcheck(m, n, 4, traceback=True, plain=plain, words_per_lane=wpl,
+                                      strip_rows=512) == 0, (wpl, plain)
+
+
 def test_packer_short_batch_full_size():
     ps = inputs.batch_short(65536)
     m = [p.x.size for p in ps]
