@@ -20,6 +20,9 @@ struct PrepArgs {
     const uint64_t *seg_len;   // region length in elements
     const uint8_t *seg_shift;  // log2 of the stream scale (words_per_lane * 512)
     uint32_t nseg;
+    const uint32_t *blk_seg;   // region of each 64-element block of the stream
+    uint64_t nblk;             // 64-element blocks in the stream (regions are
+                               // whole blocks, laid out back to back)
     uint16_t *ystream;         // element = code << seg_shift
     uint32_t sentinel;         // code whose match mask is zero (= alphabet size)
     uint64_t *out_len;         // zeroed here (per pair)

@@ -133,6 +133,7 @@ struct lcs_batch {
     std::vector<uint64_t> diag_off_host;
     uint32_t *pair_m = nullptr, *pair_n = nullptr;
     uint64_t *seg_yoff = nullptr, *seg_begin = nullptr, *seg_len = nullptr;
+    uint32_t *blk_seg = nullptr;   // region of each 64-element block of the Y stream
     uint32_t *seg_n = nullptr, *seg_pre = nullptr;
     uint8_t *seg_shift = nullptr;
     uint16_t *ystream = nullptr;
@@ -405,6 +406,7 @@ static size_t carve(lcs_batch *b, char *base) {
     b->seg_n = cv.take<uint32_t>(ns + 1);
     b->seg_pre = cv.take<uint32_t>(ns + 1);
     b->seg_shift = cv.take<uint8_t>(ns + 1);
+    b->blk_seg = cv.take<uint32_t>(p.ys_elems / 64 + 1);
     b->cls.resize(p.classes.size());
     for (size_t ci = 0; ci < p.classes.size(); ++ci) {
         const ClassPlan &C = p.classes[ci];
@@ -683,6 +685,15 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     UP(bp->seg_n, s_n.data(), ns * 4);
     UP(bp->seg_pre, s_pre.data(), ns * 4);
     UP(bp->seg_shift, s_shift.data(), ns);
+    {
+        // regions are whole 64-element blocks, back to back
+        std::vector<uint32_t> bs(p.ys_elems / 64, 0);
+        for (size_t k = 0; k < ns; ++k) {
+            const uint64_t b0 = p.segs[k].begin / 64, nb = (p.segs[k].len + 63) / 64;
+            for (uint64_t q = b0; q < b0 + nb && q < bs.size(); ++q) bs[q] = (uint32_t)k;
+        }
+        UP(bp->blk_seg, bs.data(), bs.size() * 4);
+    }
     for (size_t ci = 0; ci < p.classes.size(); ++ci) {
         const ClassPlan &C = p.classes[ci];
         ClassDev &D = bp->cls[ci];
@@ -806,6 +817,8 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
     pa.seg_len = b->seg_len;
     pa.seg_shift = b->seg_shift;
     pa.nseg = (uint32_t)p.segs.size();
+    pa.blk_seg = b->blk_seg;
+    pa.nblk = p.ys_elems / 64;
     pa.ystream = b->ystream;
     pa.sentinel = (uint32_t)b->sigma;
     pa.out_len = b->out_len;

@@ -548,6 +548,14 @@ std::string check_plan(const std::vector<PairShape> &pairs, const Plan &p) {
     for (size_t k = 1; k < iv.size(); ++k)
         if (iv[k].first < iv[k - 1].second) return "stream regions overlap";
     if (!iv.empty() && iv.back().second > p.ys_elems) return "stream region beyond the stream";
+    // ... and tile the stream in whole 64-element blocks, back to back (the
+    // stream kernel finds a block's region from a per-block table)
+    uint64_t at = 0;
+    for (const Segment &sg : p.segs) {
+        if (sg.begin != at) return "stream regions not back to back";
+        at += (sg.len + 63) / 64 * 64;
+    }
+    if (at != p.ys_elems) return "stream length";
     return std::string();
 }
 
