@@ -32,6 +32,16 @@ def concurrency(start: np.ndarray, end: np.ndarray):
     return t[o], np.cumsum(d[o])
 
 
+def chain_depth(feeder: np.ndarray) -> np.ndarray:
+    """Place of each item in its chain (0: fed by no item), from the feeder
+    links; a feeder always comes earlier in the queue."""
+    d = np.zeros(len(feeder), dtype=np.int64)
+    for k, f in enumerate(feeder.tolist()):
+        if f >= 0:
+            d[k] = d[f] + 1
+    return d
+
+
 def summarize(rec: np.ndarray, near_full: float = 0.9) -> Dict[str, float]:
     """Figures of one pass (records as returned by ``Batch.fill_trace``).
 
@@ -47,8 +57,12 @@ def summarize(rec: np.ndarray, near_full: float = 0.9) -> Dict[str, float]:
                        spent waiting for its carries
     simd_steps_spread  max over mean of the column steps each SIMD ran
     simd_end_spread    (last - first) SIMD finishing time over the span
+    wait_frac_by_depth wait_frac of the items at places 1, 2, ... of their
+                       chains (a chain runs at the pace of its slowest item)
     """
+    depth_all = chain_depth(rec["feeder"])
     r = rec[rec["ran"] != 0]
+    depth = depth_all[rec["ran"] != 0]
     if len(r) == 0:
         return {"items": 0}
     s = r["start_ns"].astype(np.int64)
@@ -79,4 +93,7 @@ def summarize(rec: np.ndarray, near_full: float = 0.9) -> Dict[str, float]:
         "wait_frac": float(w[chained].sum()) / float(steps_time) if steps_time else 0.0,
         "simd_steps_spread": float(steps.max() / steps.mean()),
         "simd_end_spread": float(simd_end.max() - simd_end.min()) / span if span else 0.0,
+        "wait_frac_by_depth": [
+            round(float(w[depth == d].sum()) / float(max(1, (e - f)[depth == d].sum())), 4)
+            for d in range(1, int(depth.max()) + 1)],
     }

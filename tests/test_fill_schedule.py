@@ -52,6 +52,22 @@ def test_simd_key_separates_every_field():
     assert len(set(k[:6].tolist())) == 6
 
 
+def test_chain_depth_and_waits_by_depth():
+    # chains 0 -> 1 -> 3 and 2 -> 4; item 5 alone
+    r = _rec([
+        (0, 0, 100, 0, 1, -1, A, 1),
+        (0, 0, 100, 10, 1, 0, A, 1),
+        (0, 0, 100, 0, 1, -1, B, 1),
+        (0, 0, 100, 30, 1, 1, B, 1),
+        (0, 0, 50, 5, 1, 2, A, 1),
+        (0, 0, 100, 0, 1, -1, B, 1),
+    ])
+    assert list(fill_schedule.chain_depth(r["feeder"])) == [0, 1, 0, 2, 1, 0]
+    s = fill_schedule.summarize(r)
+    assert s["wait_frac_by_depth"] == [pytest.approx(15 / 150), pytest.approx(30 / 100)]
+    assert s["wait_frac"] == pytest.approx(45 / 250)
+
+
 def test_empty_and_unrun():
     assert fill_schedule.summarize(_rec([]))["items"] == 0
     assert fill_schedule.summarize(_rec([(0, 0, 5, 0, 1, -1, A, 0)]))["items"] == 0
