@@ -175,3 +175,25 @@ def serve_stream(rate_hz: float, count: int, seed_offset: int = 51,
         y = random_seq(g, ly, ALPHABETS[al])
         out.append(Request(float(t[k]), x, y, al, bool(g.integers(0, 2))))
     return out
+
+
+def serve_set(count: int = 24, seed_offset: int = 61, lo: int = 10000,
+              hi: int = 100000) -> List[Request]:
+    """A fixed set of serving-scale requests (arrival times 0): |X| and |Y|
+    log-uniform in [lo, hi], alphabets cycling dna/protein/byte, traceback
+    for every other request; every third request is related (Y = X mutated
+    at a rate in [5%, 30%]), the others unrelated (independent Y)."""
+    g = rng(seed_offset)
+    names = ["dna", "protein", "byte"]
+    out = []
+    for k in range(count):
+        al = names[k % 3]
+        lx = int(np.floor(np.exp(g.uniform(np.log(lo), np.log(hi)))))
+        x = random_seq(g, lx, ALPHABETS[al])
+        if k % 3 == 1:
+            y, _ = mutate(g, x, float(g.uniform(0.05, 0.30)), ALPHABETS[al])
+        else:
+            ly = int(np.floor(np.exp(g.uniform(np.log(lo), np.log(hi)))))
+            y = random_seq(g, ly, ALPHABETS[al])
+        out.append(Request(0.0, x, y, al, k % 2 == 0))
+    return out
