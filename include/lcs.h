@@ -198,6 +198,27 @@ lcs_status lcs_traceback_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t cou
                                uint64_t arena_cap, uint64_t *out_offsets,
                                uint64_t *out_lens);
 
+/* Allocation-free form of lcs_traceback_batch, for callers that cannot
+ * allocate device memory (code inside HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * lcs_traceback_batch; every byte of device memory the batch needs (inputs,
+ * plan tables, checkpoints, bitmaps, queue counters, outputs before the copy
+ * back) is carved from one fixed array of lcs_noalloc_scratch_bytes() bytes
+ * that each device holds from library load until the process ends.  Calls no
+ * hipMalloc/hipFree and creates no HIP objects; uses the context's stream and
+ * blocks until done.  A batch that needs more than the fixed array fails with
+ * LCS_ERR_NOMEM before any launch (lcs_last_error() names both sizes).  Calls
+ * on one device share its array: they are serialised inside the process (a
+ * call holds the device's array until its results are copied back), and
+ * every pass clears what must start at zero. */
+lcs_status lcs_traceback_batch_noalloc(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
+                                       const lcs_alphabet *alphabet, uint8_t *out_arena,
+                                       uint64_t arena_cap, uint64_t *out_offsets,
+                                       uint64_t *out_lens);
+
+/* Size in bytes of the fixed scratch array of lcs_traceback_batch_noalloc. */
+uint64_t lcs_noalloc_scratch_bytes(void);
+
 /* Plan and upload a batch without running it.  The input bytes are copied to
  * device memory; the caller's host buffers may be released afterwards.
  * flags: LCS_WANT_TRACEBACK | LCS_USE_GRAPH | LCS_THRESHOLD | LCS_FILL_TRACE.

@@ -155,6 +155,7 @@ struct lcs_batch {
     hipGraphExec_t gexec = nullptr;
     bool ran = false;
     bool timed_fill = false;     // the last pass recorded the fill events
+    bool no_events = false;      // created without HIP events (allocation-free entry point)
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -186,6 +187,43 @@ static lcs_status dev_err(hipError_t e) {
             return dev_err(e_);                        \
         }                                              \
     } while (0)
+
+// --------------------------------------------------------------------------
+// fixed device scratch of the allocation-free entry point
+// --------------------------------------------------------------------------
+
+// Every device this library runs on holds one copy of this array from the
+// moment the library's code object is loaded until the process ends.  In
+// host code its name only stands in for the symbol: the device address of a
+// device's copy comes from hipGetSymbolAddress with that device current
+// (lcs_create does this once per device) and is the only handle host code
+// passes on.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+struct ScratchSlot {
+    std::mutex use;            // held for the whole of one call on the device
+    bool resolved = false;
+    void *ptr = nullptr;       // this device's copy of `scratch`
+    hipError_t err = hipSuccess;
+};
+static ScratchSlot g_scratch[kMaxDevices];
+static std::mutex g_scratch_init;
+
+// Resolve the device address of `scratch` on `device` (which must be
+// current), once per device.
+static void resolve_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_init);
+    ScratchSlot &sl = g_scratch[device];
+    if (sl.resolved) return;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    sl.err = e;
+    sl.ptr = e == hipSuccess ? ptr : nullptr;
+    sl.resolved = true;
+}
 
 // Build the byte -> code table: codes 0..size-1 in the order the alphabet
 // lists its symbols; valid[b] says whether byte b belongs to the alphabet.
@@ -313,6 +351,7 @@ extern "C" lcs_status lcs_create(lcs_ctx **out, int device, size_t mem_budget_by
         return LCS_ERR_DEVICE;
     }
     HIP_TRY(hipSetDevice(device));
+    resolve_scratch(device);
     std::unique_ptr<lcs_ctx> c(new (std::nothrow) lcs_ctx());
     if (!c) return LCS_ERR_NOMEM;
     c->device = device;
@@ -526,7 +565,7 @@ static uint32_t resident_grid(lcs_ctx *ctx, const void *fn, size_t lds, uint64_t
 static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t count,
                               const lcs_alphabet *alphabet, uint32_t flags,
                               const lcs_tuning *tuning, lcs_batch **out,
-                              const BatchHooks *hooks = nullptr) {
+                              const BatchHooks *hooks = nullptr, bool no_events = false) {
     if (!ctx || !out) return LCS_ERR_ARG;
     if (flags & ~(uint32_t)(LCS_WANT_TRACEBACK | LCS_USE_GRAPH | LCS_THRESHOLD | LCS_FILL_TRACE))
         return LCS_ERR_ARG;
@@ -788,8 +827,10 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         hipMemcpyAsync(bp->dev, image.data(), bp->upload_bytes, hipMemcpyHostToDevice, st0) != hipSuccess)
         return fail(LCS_ERR_DEVICE);
     if (hipStreamSynchronize(st0) != hipSuccess) return fail(LCS_ERR_DEVICE);
-    for (hipEvent_t &ev : bp->ev)
-        if (hipEventCreate(&ev) != hipSuccess) return fail(LCS_ERR_DEVICE);
+    bp->no_events = no_events;
+    if (!no_events)
+        for (hipEvent_t &ev : bp->ev)
+            if (hipEventCreate(&ev) != hipSuccess) return fail(LCS_ERR_DEVICE);
     *out = bp;
     return LCS_OK;
 }
@@ -1036,9 +1077,9 @@ static lcs_status launch_pass(lcs_batch *b, bool eager) {
         HIP_TRY(hipEventRecord(b->ev[3], s));
         b->timed_fill = false;
     } else {
-        lcs_status st = enqueue(b, s, true);
+        lcs_status st = enqueue(b, s, !b->no_events);
         if (st) return st;
-        b->timed_fill = true;
+        b->timed_fill = !b->no_events;
     }
     b->ran = true;
     return LCS_OK;
@@ -1378,6 +1419,69 @@ extern "C" lcs_status lcs_traceback_batch(lcs_ctx *ctx, const lcs_pair *pairs, u
     free_batch(b);
     return st;
 }
+
+// --------------------------------------------------------------------------
+// allocation-free entry point
+// --------------------------------------------------------------------------
+
+namespace {
+struct ScratchUse {
+    void *ptr;
+    size_t cap;
+};
+void *scratch_alloc(void *user, size_t bytes) {
+    ScratchUse *u = (ScratchUse *)user;
+    if (bytes > u->cap) {
+        std::snprintf(g_last_error, sizeof g_last_error,
+                      "batch needs %zu bytes of device scratch; the fixed scratch holds %zu", bytes,
+                      u->cap);
+        return nullptr;
+    }
+    return u->ptr;
+}
+void scratch_release(void *, void *) {}
+}  // namespace
+
+extern "C" lcs_status lcs_traceback_batch_noalloc(lcs_ctx *ctx, const lcs_pair *pairs,
+                                                  uint64_t count, const lcs_alphabet *alphabet,
+                                                  uint8_t *out_arena, uint64_t arena_cap,
+                                                  uint64_t *out_offsets, uint64_t *out_lens) {
+    if (!ctx || (count && (!out_offsets || !out_lens))) return LCS_ERR_ARG;
+    lcs_status st = check_pairs(pairs, count);
+    if (st) return st;
+    uint64_t worst = 0;
+    for (uint64_t k = 0; k < count; ++k) worst += std::min(pairs[k].m, pairs[k].n);
+    if (arena_cap < worst) return LCS_ERR_BUFFER;
+    if (worst && !out_arena) return LCS_ERR_ARG;
+    if (ctx->device < 0 || ctx->device >= kMaxDevices) return LCS_ERR_DEVICE;
+    ScratchSlot &sl = g_scratch[ctx->device];
+    if (!sl.resolved || !sl.ptr) {
+        if (sl.resolved) note_error("hipGetSymbolAddress(scratch)", sl.err);
+        else std::snprintf(g_last_error, sizeof g_last_error, "device scratch not resolved");
+        return LCS_ERR_DEVICE;
+    }
+    // one call at a time per device: the scratch keeps the last call's
+    // contents, and every pass clears what must start at zero itself
+    std::lock_guard<std::mutex> lk(sl.use);
+    ScratchUse use{sl.ptr, kNoAllocScratchBytes};
+    BatchHooks hooks;
+    hooks.stream = ctx->stream;
+    hooks.alloc = scratch_alloc;
+    hooks.release = scratch_release;
+    hooks.user = &use;
+    lcs_batch *b = nullptr;
+    st = build_batch(ctx, pairs, count, alphabet, LCS_WANT_TRACEBACK, nullptr, &b, &hooks, true);
+    if (st) return st;
+    st = launch_pass(b, true);
+    if (!st) st = lcs_batch_tracebacks(b, out_arena, arena_cap, out_offsets, out_lens);
+    // nothing of this call may still run on the scratch once the next call
+    // can take it
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess && !st) st = LCS_ERR_DEVICE;
+    free_batch(b);
+    return st;
+}
+
+extern "C" uint64_t lcs_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
 
 // --------------------------------------------------------------------------
 // host-only planning checks

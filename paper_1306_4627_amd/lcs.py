@@ -46,7 +46,7 @@ class LcsError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
         detail = ""
-        if status == LCS_ERR_DEVICE:
+        if status in (LCS_ERR_DEVICE, LCS_ERR_NOMEM):
             detail = " [" + _lib.lcs_last_error().decode(errors="replace") + "]"
         msg = f"{what}: {status_str(status)} ({status})" if what else status_str(status)
         super().__init__(msg + detail)
@@ -133,6 +133,11 @@ def _load() -> ctypes.CDLL:
     lib.lcs_traceback_batch.argtypes = [vp, P(lcs_pair), u64, P(lcs_alphabet), u8p, u64,
                                         u64p, u64p]
     lib.lcs_traceback_batch.restype = i32
+    lib.lcs_traceback_batch_noalloc.argtypes = [vp, P(lcs_pair), u64, P(lcs_alphabet), u8p, u64,
+                                                u64p, u64p]
+    lib.lcs_traceback_batch_noalloc.restype = i32
+    lib.lcs_noalloc_scratch_bytes.argtypes = []
+    lib.lcs_noalloc_scratch_bytes.restype = u64
     lib.lcs_batch_create.argtypes = [vp, P(lcs_pair), u64, P(lcs_alphabet), ctypes.c_uint32,
                                      P(lcs_tuning), P(vp)]
     lib.lcs_batch_create.restype = i32
@@ -349,6 +354,27 @@ def lcs_traceback_batch(ctx: Context, pairs, alphabet="dna") -> List[bytes]:
                                     cap, offs.ctypes.data_as(P64), lens.ctypes.data_as(P64)),
            "lcs_traceback_batch")
     return [arena[int(o):int(o) + int(l)].tobytes() for o, l in zip(offs[:pp.count], lens[:pp.count])]
+
+
+def lcs_traceback_batch_noalloc(ctx: Context, pairs, alphabet="dna") -> List[bytes]:
+    """lcs_traceback_batch with every device buffer carved from the library's
+    fixed device scratch array (no device allocation)."""
+    pp = _Pairs(pairs)
+    al = _alpha(alphabet)
+    cap = sum(min(len(_as_u8(x)), len(_as_u8(y))) for x, y in pairs)
+    arena = np.zeros(max(1, cap), dtype=np.uint8)
+    offs = np.zeros(max(1, pp.count), dtype=np.uint64)
+    lens = np.zeros(max(1, pp.count), dtype=np.uint64)
+    P64 = ctypes.POINTER(ctypes.c_uint64)
+    _check(_lib.lcs_traceback_batch_noalloc(ctx.h, pp.ptr(), pp.count, ctypes.byref(al.c),
+                                            _u8p(arena), cap, offs.ctypes.data_as(P64),
+                                            lens.ctypes.data_as(P64)),
+           "lcs_traceback_batch_noalloc")
+    return [arena[int(o):int(o) + int(l)].tobytes() for o, l in zip(offs[:pp.count], lens[:pp.count])]
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(_lib.lcs_noalloc_scratch_bytes())
 
 
 def lcs_similarity_batch(ctx: Context, pairs, alphabet="dna") -> np.ndarray:

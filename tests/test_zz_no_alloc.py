@@ -1,0 +1,88 @@
+"""The allocation-free traceback batch (fixed device scratch array) against
+the allocating one, bit-exact, through the C ABI.
+
+Two calls in a row share the device's scratch array; the second is smaller,
+so anything the first call left behind that the second relied on being zero
+would show.  A batch larger than the array is refused before any launch.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1306_4627_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lcs():
+    from paper_1306_4627_amd import lcs as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(lcs):
+    c = lcs.Context(0)
+    yield c
+    c.close()
+
+
+def _related_pairs(g, count, lo, hi, alphabet):
+    out = []
+    for k in range(count):
+        m = int(g.integers(lo, hi + 1))
+        x = inputs.random_seq(g, m, alphabet)
+        if k % 2:
+            y, _ = inputs.mutate(g, x, float(g.uniform(0.05, 0.3)), alphabet)
+        else:
+            y = inputs.random_seq(g, int(g.integers(lo, hi + 1)), alphabet)
+        out.append((x, y))
+    return out
+
+
+def test_noalloc_matches_allocating_entry(ctx, lcs):
+    g = inputs.rng(7100)
+    # first call: 48 pairs up to 9000 rows (chained items at one and two
+    # words per lane, several strips), plus empty and one-symbol pairs
+    big = _related_pairs(g, 48, 1, 9000, inputs.DNA)
+    big += [(inputs.random_seq(g, 0, inputs.DNA), inputs.random_seq(g, 50, inputs.DNA)),
+            (inputs.random_seq(g, 1, inputs.DNA), inputs.random_seq(g, 1, inputs.DNA)),
+            (inputs.random_seq(g, 70, inputs.DNA), inputs.random_seq(g, 0, inputs.DNA))]
+    # second call: fewer and shorter pairs, another alphabet
+    small = _related_pairs(g, 9, 1, 700, inputs.PROTEIN)
+    assert lcs.noalloc_scratch_bytes() >= 1 << 20
+    for name, pairs, al in (("first", big, "dna"), ("second", small, "protein")):
+        _say(f"noalloc {name}: {len(pairs)} pairs")
+        got = lcs.lcs_traceback_batch_noalloc(ctx, pairs, al)
+        _say(f"allocating {name}: {len(pairs)} pairs")
+        want = lcs.lcs_traceback_batch(ctx, pairs, al)
+        assert got == want
+        # and both are the oracle's canonical strings
+        for (x, y), s in zip(pairs, got):
+            assert s == oracle.lcs_traceback(x, y)
+
+
+def test_noalloc_refuses_batches_beyond_the_array(ctx, lcs):
+    g = inputs.rng(7101)
+    cap = lcs.noalloc_scratch_bytes()
+    # pairs whose inputs alone exceed the array
+    n = 3_000_000
+    count = cap // (2 * n) + 1
+    big = [(inputs.random_seq(g, n, inputs.DNA), inputs.random_seq(g, n, inputs.DNA))
+           for _ in range(count)]
+    _say(f"noalloc refusal: {count} pairs of {n} x {n}")
+    with pytest.raises(lcs.LcsError) as ei:
+        lcs.lcs_traceback_batch_noalloc(ctx, big, "dna")
+    assert ei.value.status == lcs.LCS_ERR_NOMEM
+    assert "scratch" in str(ei.value)
+    # the array is still usable afterwards
+    pairs = _related_pairs(g, 5, 1, 400, inputs.DNA)
+    _say("noalloc after refusal")
+    assert lcs.lcs_traceback_batch_noalloc(ctx, pairs, "dna") == lcs.lcs_traceback_batch(ctx, pairs, "dna")
