@@ -31,13 +31,33 @@ _lib: Optional[ctypes.CDLL] = None
 
 
 def build_oracle(force: bool = True) -> str:
-    """Compile the C oracle with gcc into ``oracle/liblcs_oracle.so``."""
+    """Compile the C oracle with gcc into ``oracle/liblcs_oracle.so``.
+
+    Built for the generic x86-64 target, so the shared object runs on any
+    host the tree is copied to."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC])
+            ["gcc", "-O3", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def use_native_build() -> str:
+    """Rebuild the oracle with ``-O3 -march=native`` for the host this runs
+    on and load that copy instead (for timing the oracle as a CPU baseline;
+    the arithmetic is the same source).  Must be called before any other
+    oracle call in the process."""
+    global _lib, _LIB
+    if _lib is not None:
+        raise RuntimeError("use_native_build() must come before the first oracle call")
+    native = os.path.join(_HERE, "liblcs_oracle_native.so")
+    tmp = native + ".tmp"
+    subprocess.check_call(
+        ["gcc", "-O3", "-march=native", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC])
+    os.replace(tmp, native)
+    _LIB = native
+    return native
 
 
 def _load() -> ctypes.CDLL:

@@ -11,6 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 import pytest
 
+import golden_data as gd
 import oracle
 from paper_1306_4627_amd import inputs
 
@@ -348,61 +349,78 @@ def test_error_paths_leave_outputs_untouched(ctx, lcs):
 
 def test_full_pair_dna_4096(ctx, lcs):
     p = inputs.pair_dna_4096()
+    g = gd.pair("pair_dna_4096")
+    assert g.input_sha256 == gd.input_digest([(p.x, p.y)]), "input generator changed"
     _say("full 4096x4096 pair")
-    assert lcs.lcs_length(ctx, p.x, p.y, "dna") == oracle.lcs_length(p.x, p.y)
-    assert lcs.lcs_traceback(ctx, p.x, p.y, "dna") == oracle.lcs_traceback(p.x, p.y)
+    assert lcs.lcs_length(ctx, p.x, p.y, "dna") == g.length
+    s = lcs.lcs_traceback(ctx, p.x, p.y, "dna")
+    assert (len(s), gd.string_digest(s)) == (g.length, g.string_sha256)
 
 
-def test_full_batch_short_sampled(ctx, lcs):
+def test_full_batch_short(ctx, lcs):
+    # every one of the 65536 lengths against the oracle's (stored)
     ps = inputs.batch_short()
     pairs = [(p.x, p.y) for p in ps]
-    _say("full short batch (65536 pairs)")
+    g = gd.batch_short()
+    assert g.input_sha256 == gd.input_digest(pairs), "input generator changed"
+    _say("full short batch (65536 pairs), graph replays")
     with lcs.Batch(ctx, pairs, "protein", graph=True) as b:
+        for rep in range(2):
+            b.run()
+            L = b.lengths()
+            bad = np.flatnonzero(L != g.lengths)
+            assert bad.size == 0, f"replay {rep}: {bad.size} pairs differ, first {bad[:8]}"
+
+
+def test_full_batch_short_autotuned(ctx, lcs):
+    # the benchmark's launch configuration: the autotuner's choice
+    ps = inputs.batch_short()
+    pairs = [(p.x, p.y) for p in ps]
+    g = gd.batch_short()
+    _say("full short batch, autotuned")
+    tuning, _ = lcs.autotune(ctx, pairs, "protein", traceback=False, graph=True)
+    with lcs.Batch(ctx, pairs, "protein", graph=True, **tuning) as b:
         b.run()
         L = b.lengths()
-    g = np.random.default_rng(1)
-    idx = np.concatenate([g.choice(len(pairs), 3000, replace=False), np.arange(64)])
-    want = _oracle_lengths([pairs[k] for k in idx])
-    assert np.array_equal(L[idx], want)
-    lens = np.array([min(p.x.size, p.y.size) for p in ps])
-    assert np.all(L <= lens) and np.all(L > 0)
+    assert np.array_equal(L, g.lengths), tuning
 
 
-def test_full_batch_related_sampled(ctx, lcs):
+@pytest.mark.skipif(not gd.exists("full_batch_related.txt"), reason="golden not written")
+def test_full_batch_related(ctx, lcs):
+    # every one of the 4096 lengths and strings against the oracle's (stored)
     ps = inputs.batch_related()
     pairs = [(p.x, p.y) for p in ps]
-    _say("full related batch (4096 pairs, tracebacks)")
-    with lcs.Batch(ctx, pairs, "dna", traceback=True, graph=True) as b:
-        b.run()
-        L = b.lengths()
-        S = b.tracebacks()
-    # properties on every pair
-    for p, l, s in zip(ps, L, S):
-        assert len(s) == l <= min(p.x.size, p.y.size)
-        assert l >= p.x.size - (p.log.substitutions + p.log.deletions)
-    sizes = np.array([p.cells for p in ps])
-    order = np.argsort(sizes)
-    idx = list(order[:40]) + list(order[len(order) // 2: len(order) // 2 + 8]) + list(order[-2:])
-    sub = [pairs[k] for k in idx]
-    want_L = _oracle_lengths(sub)
-    assert np.array_equal(L[idx], want_L)
-    want_S = _oracle_tracebacks(sub)
-    for k, w in zip(idx, want_S):
-        assert S[k] == w, f"pair {k}"
-    for k in range(0, len(ps), 97):   # common-subsequence check on a spread
-        assert oracle.is_subsequence(S[k], pairs[k][0].tobytes())
-        assert oracle.is_subsequence(S[k], pairs[k][1].tobytes())
+    g = gd.batch_related()
+    assert g.input_sha256 == gd.input_digest(pairs), "input generator changed"
+    _say("full related batch (4096 pairs, tracebacks), autotuned, graph replays")
+    tuning, _ = lcs.autotune(ctx, pairs, "dna", traceback=True, graph=True)
+    with lcs.Batch(ctx, pairs, "dna", traceback=True, graph=True, **tuning) as b:
+        for rep in range(2):
+            b.run()
+            L = b.lengths()
+            S = b.tracebacks()
+            bad = np.flatnonzero(L != g.lengths)
+            assert bad.size == 0, f"replay {rep}: {bad.size} lengths differ, first {bad[:8]}"
+            bad = [k for k in range(len(S)) if gd.string_digest(S[k])[:32] != g.sha_prefix[k]]
+            assert not bad, f"replay {rep}: {len(bad)} strings differ, first {bad[:8]}"
 
 
+@pytest.mark.skipif(not gd.exists("full_pair_long_related.txt"), reason="golden not written")
 def test_full_long_related_pair(ctx, lcs):
     p = inputs.pair_long_related()
+    g = gd.pair("pair_long_related")
+    assert g.input_sha256 == gd.input_digest([(p.x, p.y)]), "input generator changed"
     _say("full long related pair 262144")
-    L = lcs.lcs_length(ctx, p.x, p.y, "dna")
+    assert lcs.lcs_length(ctx, p.x, p.y, "dna") == g.length
     S = lcs.lcs_traceback(ctx, p.x, p.y, "dna")
-    assert len(S) == L
-    assert L >= p.x.size - (p.log.substitutions + p.log.deletions)
-    assert L <= min(p.x.size, p.y.size)
-    assert oracle.is_subsequence(S, p.x.tobytes()) and oracle.is_subsequence(S, p.y.tobytes())
+    assert (len(S), gd.string_digest(S)) == (g.length, g.string_sha256)
+    # the benchmark's resident batch of this pair, graph replays
+    with lcs.Batch(ctx, [(p.x, p.y)], "dna", traceback=True, graph=True, words_per_lane=1) as b:
+        for rep in range(2):
+            b.run()
+            assert b.lengths()[0] == g.length
+            s2 = b.tracebacks()[0]
+            assert gd.string_digest(s2) == g.string_sha256, f"replay {rep}"
 
 
 def test_long_related_pair_scaled_exact(ctx, lcs):

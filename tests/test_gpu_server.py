@@ -8,6 +8,7 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 import pytest
 
+import golden_data as gd
 import oracle
 from paper_1306_4627_amd import inputs
 
@@ -152,3 +153,46 @@ def test_server_errors_and_cancel(ctx, lcs):
         L, s, _ = srv.result(t1)
         assert s == x.tobytes() and L == x.size
         assert srv.poll(t1) == lcs.LCS_ERR_ARG      # collected tickets are gone
+
+
+def _check_golden(k, e, L, s):
+    assert L == e.length, f"request {k}: length {L} != {e.length}"
+    if e.traceback:
+        assert s is not None and gd.string_digest(s) == e.string_sha256, f"request {k}: string differs"
+    else:
+        assert s is None
+
+
+def test_server_serving_scale_requests_in_a_stream(ctx, lcs):
+    # requests of 10^4..10^5 symbols over DNA, protein and all 256 bytes, half
+    # with tracebacks, a third related (walks that stay near the diagonal) and
+    # the rest unrelated (walks that fall back to the sequential seal); they
+    # arrive 3 ms apart, so later ones are admitted while earlier ones run.
+    # Every result against the oracle's (stored), in the stream and alone.
+    import time
+    reqs = inputs.serve_set()
+    digest, want = gd.serve_set()
+    assert digest == gd.input_digest([(r.x, r.y) for r in reqs]), "input generator changed"
+    _say(f"server serving-scale stream, {len(reqs)} requests")
+    with lcs.Server(ctx, mem_budget_bytes=4 << 30) as srv:
+        t0 = time.perf_counter()
+        tickets = []
+        for k, r in enumerate(reqs):
+            while time.perf_counter() - t0 < 0.003 * k:
+                pass
+            tickets.append(srv.submit(r.x, r.y, ALPHA[r.alphabet], traceback=r.want_traceback))
+        for k, t in enumerate(tickets):
+            assert srv.wait(t, 120_000_000) == 0, k
+            L, s, _ = srv.result(t)
+            _check_golden(k, want[k], L, s)
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["batches"] >= 2
+    assert st["max_inflight"] >= 2, st      # their work overlapped on the device
+    _say("server serving-scale requests alone")
+    with lcs.Server(ctx, mem_budget_bytes=4 << 30, streams=1) as srv:
+        for k, r in enumerate(reqs):
+            t = srv.submit(r.x, r.y, ALPHA[r.alphabet], traceback=r.want_traceback)
+            assert srv.wait(t, 120_000_000) == 0, k
+            L, s, _ = srv.result(t)
+            _check_golden(k, want[k], L, s)
