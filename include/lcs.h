@@ -118,7 +118,23 @@ typedef struct lcs_batch lcs_batch;
  *                    wait on the one below; link_items caps a run's length
  *                    (default 1: a long pair always starts a new item; on the
  *                    4096-pair related batch 8-32 pack 6-8% fewer lane-steps
- *                    but run no faster).  Results do not depend on it. */
+ *                    but run no faster).  Results do not depend on it.
+ *  tb_round_kib    : traceback history held at once, in KiB (0 = automatic).
+ *                    The fast form stores the checkpoints and carry bits of
+ *                    every work item during the fill, about m*n/64 bits per
+ *                    pair.  With rounds the fill stores nothing but lengths
+ *                    and the carry words handed between the items of a long
+ *                    pair (16 bytes per 64 columns per 4096*words_per_lane
+ *                    rows); the
+ *                    items are then refilled round by round, top of each pair
+ *                    first, each round keeping the history of at most
+ *                    tb_round_kib KiB of items and walking the strips they
+ *                    hold from where the previous round's walk left off.
+ *                    Automatic: one pass when the whole history fits the
+ *                    memory left, else rounds sized to what is left after the
+ *                    batch's other buffers.  The history of one work item is
+ *                    8*(words_per_lane+1) bytes per column (the smallest
+ *                    round); results do not depend on it. */
 typedef struct {
     int32_t words_per_lane;
     int32_t ckpt_interval;
@@ -128,6 +144,7 @@ typedef struct {
     int32_t tb_tiles;
     int32_t tb_bands;
     int32_t link_items;
+    int32_t tb_round_kib;
 } lcs_tuning;
 
 /* What a batch was planned into (filled by lcs_batch_info). */
@@ -142,6 +159,10 @@ typedef struct {
     int32_t ckpt_interval;   /* as chosen (0 without traceback) */
     int32_t classes;         /* kernel launches per run (fill) */
     int32_t flags;           /* LCS_WANT_TRACEBACK / LCS_USE_GRAPH as planned */
+    int32_t tb_rounds;       /* traceback rounds (0: one pass, full history) */
+    int32_t reserved;
+    uint64_t history_bytes;  /* device bytes of traceback history (checkpoints
+                                and carry bits, or the round buffer) */
 } lcs_batch_stats;
 
 /* Text for a status code; never NULL; static storage. */
@@ -206,8 +227,10 @@ lcs_status lcs_traceback_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t cou
  * back) is carved from one fixed array of lcs_noalloc_scratch_bytes() bytes
  * that each device holds from library load until the process ends.  Calls no
  * hipMalloc/hipFree and creates no HIP objects; uses the context's stream and
- * blocks until done.  A batch that needs more than the fixed array fails with
- * LCS_ERR_NOMEM before any launch (lcs_last_error() names both sizes).  Calls
+ * blocks until done.  A batch whose full traceback history would not fit the
+ * array runs its traceback in rounds (see lcs_tuning.tb_round_kib); one that
+ * needs more than the array even so fails with LCS_ERR_NOMEM before any
+ * launch (lcs_last_error() names both sizes).  Calls
  * on one device share its array: they are serialised inside the process (a
  * call holds the device's array until its results are copied back), and
  * every pass clears what must start at zero. */

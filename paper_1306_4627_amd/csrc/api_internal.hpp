@@ -17,6 +17,9 @@ struct BatchHooks {
     void *(*alloc)(void *user, size_t bytes) = nullptr;    // device memory instead of hipMalloc
     void (*release)(void *user, void *ptr) = nullptr;      // returns it
     void *user = nullptr;
+    // device bytes the batch may hold at most (0: no limit known); a
+    // traceback batch whose full history would not fit runs in rounds
+    size_t avail = 0;
 };
 
 // lcs_batch_create with hooks (hooks may be null).

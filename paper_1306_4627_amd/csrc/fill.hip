@@ -208,7 +208,7 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
             }
             return;
         }
-        const uint32_t item = a.item_begin + ticket;
+        const uint32_t item = a.item_list ? a.item_list[a.item_begin + ticket] : a.item_begin + ticket;
         const uint64_t taken = a.trace ? __builtin_amdgcn_s_memrealtime() : 0;
 
         const size_t li = (size_t)item * 64 + lane;
@@ -502,6 +502,7 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
         if (THR && stopped) continue;
 
         // ---- length: zero bits among the valid rows ----
+        if (!a.out_len) continue;
         const uint32_t zeros = lane_zeros<WPL>(vlo, vhi, pair, word0, m);
         if (zeros) atomicAdd((unsigned long long *)(a.out_len + pair), (unsigned long long)zeros);
     }

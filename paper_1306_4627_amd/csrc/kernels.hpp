@@ -57,7 +57,7 @@ struct FillArgs {
     const uint32_t *ln_word0;
     const uint32_t *ln_skew;
     const uint64_t *ln_ys;
-    uint64_t *out_len;
+    uint64_t *out_len;         // null: lengths not added (traceback rounds' refills)
     uint64_t *ckpt;
     uint32_t *cbits;
     uint64_t *xfer;            // hand-over words, two per chunk per feeder (zeroed)
@@ -65,6 +65,9 @@ struct FillArgs {
     uint32_t *error;           // set to 1 when a bounded wait runs out
     uint32_t item_begin;
     uint32_t item_end;
+    // optional: the items to run are item_list[item_begin .. item_end)
+    // instead of the range itself (traceback rounds refill a set of items)
+    const uint32_t *item_list;
     uint32_t prio_half;        // half the longest item's steps: scale of the wave priorities
     uint32_t spin_limit;       // polls before a wait gives up
     int32_t sigma;             // code sigma is the zero-mask sentinel
@@ -117,7 +120,12 @@ struct TbArgs {
     const uint32_t *tb_band0;   //   first entry of its band crossings
     const uint32_t *tb_strip0;  //   first entry of its strip results
     const uint32_t *tk_t;       // per ticket: traceback entry
-    const uint32_t *tk_s;       // per ticket: strip (speculative and fix-up passes)
+    const uint32_t *tk_s;       // per ticket: strip (speculative and fix-up passes;
+                                // speculative with kFromAbove: the strip starts at
+                                // the column the walk left the strip above); seal
+                                // pass: top strip of the group, or null for the
+                                // pair's top strip
+    const uint32_t *tk_lo;      // seal pass: bottom strip of the group, or null for 0
     uint32_t nticket;
     uint32_t *queue;
     uint32_t *cross;            // per band: column where the speculative walk leaves it

@@ -83,6 +83,17 @@ struct ClassDev {
     std::vector<uint32_t> pl_pair;     // pair of each launch
     std::vector<uint32_t> pl_begin, pl_end, pl_tb;  // item range, index in tb list
     std::vector<uint32_t> pl_sp, pl_nsp, pl_fx, pl_nfx, pl_sl;  // ticket ranges (pl_sl: -1 = none)
+    // traceback rounds: per item the history offsets in the round buffer,
+    // per round its items and tickets (device), the ranges (host), four
+    // queue counters per round (refill, speculative, fix-up, seal) and grids
+    uint32_t n_rounds = 0;
+    uint64_t *it_rb = nullptr, *it_rcb = nullptr;
+    uint32_t *rd_items = nullptr;
+    uint32_t *rd_sp_t = nullptr, *rd_sp_s = nullptr, *rd_fx_t = nullptr, *rd_fx_s = nullptr;
+    uint32_t *rd_sl_t = nullptr, *rd_sl_top = nullptr, *rd_sl_lo = nullptr;
+    uint32_t *q_round = nullptr;
+    std::vector<uint32_t> rd_item_off, rd_sp_off, rd_fx_off, rd_sl_off;
+    std::vector<uint32_t> rd_fill_grid, rd_sp_grid, rd_fx_grid, rd_sl_grid;
 };
 
 // queue counters per class (and per pair in plain mode): fill, speculative,
@@ -156,6 +167,9 @@ struct lcs_batch {
     bool ran = false;
     bool timed_fill = false;     // the last pass recorded the fill events
     bool no_events = false;      // created without HIP events (allocation-free entry point)
+    bool rounds = false;         // traceback in rounds (history of a set of items at a time)
+    uint64_t *round_buf = nullptr;
+    uint64_t history_bytes = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -271,7 +285,7 @@ static lcs_status check_tuning(const lcs_tuning *t) {
         t->ckpt_interval != 256)
         return LCS_ERR_ARG;
     if (t->persistent_waves < 0 || t->plain < 0 || t->plain > 1) return LCS_ERR_ARG;
-    if (t->link_items < 0) return LCS_ERR_ARG;
+    if (t->link_items < 0 || t->tb_round_kib < 0) return LCS_ERR_ARG;
     if (t->strip_rows < 0 || t->tb_tiles < 0 || t->tb_tiles > 8 || t->tb_bands < 0 ||
         t->tb_bands > 16 || t->tb_tiles * t->tb_bands > 64)
         return LCS_ERR_ARG;
@@ -286,6 +300,7 @@ static void fill_plan_config(PlanConfig &cfg, int sigma, uint32_t flags, const l
     cfg.plain = t && t->plain;
     cfg.strip_rows = (t && t->strip_rows) ? t->strip_rows : 4096;
     cfg.link_items = (t && t->link_items) ? t->link_items : 1;
+    cfg.round_bytes = (cfg.traceback && t && t->tb_round_kib > 0) ? (uint64_t)t->tb_round_kib * 1024 : 0;
 }
 
 static void stats_from_plan(const Plan &p, uint64_t npairs, lcs_batch_stats *out) {
@@ -301,6 +316,22 @@ static void stats_from_plan(const Plan &p, uint64_t npairs, lcs_batch_stats *out
     out->ckpt_interval = p.cfg.traceback ? p.cfg.ckpt : 0;
     out->classes = (int32_t)p.classes.size();
     out->flags = p.cfg.traceback ? (int32_t)LCS_WANT_TRACEBACK : 0;
+    uint64_t rw = 0, full = 0;
+    for (const ClassPlan &c : p.classes) {
+        out->tb_rounds = std::max<int32_t>(out->tb_rounds, (int32_t)c.n_rounds);
+        rw = std::max(rw, c.round_words);
+        full += (c.ck_words + 1) * 8 + (c.cb_words + 1) * 4;
+    }
+    if (p.cfg.traceback) out->history_bytes = p.cfg.round_bytes ? (rw + 1) * 8 : full;
+}
+
+// Planner messages to status codes.
+static lcs_status plan_status(const std::string &why) {
+    if (why.find("longer") != std::string::npos || why.find("too long") != std::string::npos ||
+        why.find("too many") != std::string::npos)
+        return LCS_ERR_TOO_LONG;
+    if (why.find("round capacity") != std::string::npos) return LCS_ERR_NOMEM;
+    return LCS_ERR_UNSUPPORTED;
 }
 
 // --------------------------------------------------------------------------
@@ -478,6 +509,19 @@ static size_t carve(lcs_batch *b, char *base) {
         D.fx_t = cv.take<uint32_t>(D.nfx + 1);
         D.fx_s = cv.take<uint32_t>(D.nfx + 1);
         D.sl_t = cv.take<uint32_t>(D.nsl + 1);
+        D.n_rounds = C.n_rounds;
+        if (C.n_rounds) {
+            D.it_rb = cv.take<uint64_t>(D.nitems);
+            D.it_rcb = cv.take<uint64_t>(D.nitems);
+            D.rd_items = cv.take<uint32_t>(C.rd_items.size() + 1);
+            D.rd_sp_t = cv.take<uint32_t>(C.rd_sp_t.size() + 1);
+            D.rd_sp_s = cv.take<uint32_t>(C.rd_sp_s.size() + 1);
+            D.rd_fx_t = cv.take<uint32_t>(C.rd_fx_t.size() + 1);
+            D.rd_fx_s = cv.take<uint32_t>(C.rd_fx_s.size() + 1);
+            D.rd_sl_t = cv.take<uint32_t>(C.rd_sl_t.size() + 1);
+            D.rd_sl_top = cv.take<uint32_t>(C.rd_sl_top.size() + 1);
+            D.rd_sl_lo = cv.take<uint32_t>(C.rd_sl_lo.size() + 1);
+        }
     }
     cv.off = (cv.off + 255) & ~(size_t)255;
     b->upload_bytes = cv.off;
@@ -491,6 +535,7 @@ static size_t carve(lcs_batch *b, char *base) {
         const ClassPlan &C = p.classes[ci];
         nz += kQueues;
         if (b->plain) nz += kQueues * C.tb_pair.size();
+        nz += kQueues * C.n_rounds;
     }
     b->zero = cv.take<uint32_t>(nz);
     b->nzero = nz;
@@ -512,13 +557,29 @@ static size_t carve(lcs_batch *b, char *base) {
     b->diag = b->zero64;
     uint64_t z64 = (b->flags & LCS_WANT_TRACEBACK) ? b->diag_words : 0;
     uint64_t zc = 1;
+    // traceback history: every item's at once, or one round buffer shared by
+    // the rounds of every class (they run one after another)
+    b->history_bytes = 0;
+    b->round_buf = nullptr;
+    if (b->rounds) {
+        uint64_t rw = 0;
+        for (const ClassPlan &C : p.classes) rw = std::max(rw, C.round_words);
+        b->round_buf = cv.take<uint64_t>(rw + 1);
+        b->history_bytes = (rw + 1) * 8;
+    }
     for (size_t ci = 0; ci < p.classes.size(); ++ci) {
         const ClassPlan &C = p.classes[ci];
         ClassDev &D = b->cls[ci];
         D.cross = cv.take<uint32_t>(C.n_bands + 1);
         D.strip_res = cv.take<uint32_t>(2 * C.n_strips + 2);
-        D.ckpt = cv.take<uint64_t>(C.ck_words + 1);
-        D.cbits = cv.take<uint32_t>(C.cb_words + 1);
+        if (b->rounds) {
+            D.ckpt = b->round_buf;
+            D.cbits = (uint32_t *)b->round_buf;
+        } else {
+            D.ckpt = cv.take<uint64_t>(C.ck_words + 1);
+            D.cbits = cv.take<uint32_t>(C.cb_words + 1);
+            if (b->flags & LCS_WANT_TRACEBACK) b->history_bytes += (C.ck_words + 1) * 8 + (C.cb_words + 1) * 4;
+        }
         D.xfer = b->zero64 ? b->zero64 + z64 : nullptr;
         z64 += C.xf_words;
         if (thr) {
@@ -536,6 +597,8 @@ static size_t carve(lcs_batch *b, char *base) {
         zc += kQueues;
         D.plain_ctr = b->zero ? b->zero + zc : nullptr;
         if (b->plain) zc += kQueues * D.ntb;
+        D.q_round = b->zero ? b->zero + zc : nullptr;
+        zc += kQueues * C.n_rounds;
     }
     return cv.off + 256;
 }
@@ -634,14 +697,38 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     if (max_wpl(sigma) == 0) return LCS_ERR_UNSUPPORTED;
     if (cfg.wpl && !wpl_fits(sigma, cfg.wpl)) return LCS_ERR_UNSUPPORTED;
     std::string why = build_plan(shapes, cfg, b->plan);
-    if (!why.empty()) {
-        if (why.find("longer") != std::string::npos || why.find("too long") != std::string::npos ||
-            why.find("too many") != std::string::npos)
-            return LCS_ERR_TOO_LONG;
-        return LCS_ERR_UNSUPPORTED;
-    }
+    if (!why.empty()) return plan_status(why);
     b->ckpt = cfg.ckpt;
-    const size_t need = carve(b.get(), nullptr);
+    b->rounds = cfg.round_bytes != 0;
+    size_t need = carve(b.get(), nullptr);
+    // A traceback whose full history does not fit the memory this batch may
+    // take runs in rounds, the round buffer sized to what the other buffers
+    // leave (shrunk until the whole batch fits, or NOMEM below).
+    if ((flags & LCS_WANT_TRACEBACK) && !b->plain && !b->rounds) {
+        size_t avail = 0;
+        if (hooks && hooks->alloc) {
+            avail = hooks->avail;
+        } else {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            avail = ctx->budget > ctx->in_use ? ctx->budget - ctx->in_use : 0;
+        }
+        if (avail && need > avail && need - b->history_bytes < avail) {
+            size_t rb = avail - (need - b->history_bytes);
+            for (int tries = 0; tries < 6 && rb >= 4096; ++tries) {
+                PlanConfig c2 = cfg;
+                c2.round_bytes = rb & ~(size_t)4095;
+                c2.link_items = 1;
+                Plan p2;
+                if (!build_plan(shapes, c2, p2).empty()) break;   // an item larger than the rounds
+                b->plan = std::move(p2);
+                b->rounds = true;
+                cfg = c2;
+                need = carve(b.get(), nullptr);
+                if (need <= avail) break;
+                rb -= std::min(rb, need - avail + 4096);
+            }
+        }
+    }
     if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
     void *mem = nullptr;
     if (hooks && hooks->alloc) {
@@ -757,14 +844,38 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         UP(D.fx_t, C.fx_t.data(), C.fx_t.size() * 4);
         UP(D.fx_s, C.fx_s.data(), C.fx_s.size() * 4);
         UP(D.sl_t, C.sl_t.data(), C.sl_t.size() * 4);
+        if (C.n_rounds) {
+            UP(D.it_rb, C.it_rb.data(), C.it_rb.size() * 8);
+            UP(D.it_rcb, C.it_rcb.data(), C.it_rcb.size() * 8);
+            UP(D.rd_items, C.rd_items.data(), C.rd_items.size() * 4);
+            UP(D.rd_sp_t, C.rd_sp_t.data(), C.rd_sp_t.size() * 4);
+            UP(D.rd_sp_s, C.rd_sp_s.data(), C.rd_sp_s.size() * 4);
+            UP(D.rd_fx_t, C.rd_fx_t.data(), C.rd_fx_t.size() * 4);
+            UP(D.rd_fx_s, C.rd_fx_s.data(), C.rd_fx_s.size() * 4);
+            UP(D.rd_sl_t, C.rd_sl_t.data(), C.rd_sl_t.size() * 4);
+            UP(D.rd_sl_top, C.rd_sl_top.data(), C.rd_sl_top.size() * 4);
+            UP(D.rd_sl_lo, C.rd_sl_lo.data(), C.rd_sl_lo.size() * 4);
+            D.rd_item_off = C.rd_item_off;
+            D.rd_sp_off = C.rd_sp_off;
+            D.rd_fx_off = C.rd_fx_off;
+            D.rd_sl_off = C.rd_sl_off;
+        }
         const int cap = tuning ? tuning->persistent_waves : 0;
         {
             const int fw = fill_block(C.wpl, sigma) / 64;   // waves per fill work-group
             D.fill_waves = fw;
-            const int mode = fill_mode(flags);
+            // with traceback rounds the pass's fill stores no history
+            const int mode = bp->rounds ? (int)kFillLength : fill_mode(flags);
             D.fill_grid = resident_grid(ctx, fill_symbol(C.wpl, mode, raw_stream(sigma, C.wpl)),
                                         fill_lds_bytes(C.wpl, sigma, mode), (D.nitems + fw - 1) / fw,
                                         cap > 0 ? (cap + fw - 1) / fw : 0, 64 * fw);
+            const void *tfn = fill_symbol(C.wpl, kFillTraceback, raw_stream(sigma, C.wpl));
+            const size_t tlds = fill_lds_bytes(C.wpl, sigma, kFillTraceback);
+            for (uint32_t r = 0; r < C.n_rounds; ++r) {
+                const uint32_t ni = C.rd_item_off[r + 1] - C.rd_item_off[r];
+                D.rd_fill_grid.push_back(resident_grid(ctx, tfn, tlds, (ni + fw - 1) / fw,
+                                                       cap > 0 ? (cap + fw - 1) / fw : 0, 64 * fw));
+            }
         }
         // the fill's wave priorities are set by the steps an item has left,
         // at fractions of the longest item
@@ -794,6 +905,14 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
             D.sp_grid = resident_grid(ctx, sym, lds, (D.nsp + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
             D.fx_grid = resident_grid(ctx, sym, lds, (D.nfx + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
             D.sl_grid = resident_grid(ctx, sym, lds, (D.nsl + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
+            for (uint32_t r = 0; r < C.n_rounds; ++r) {
+                const uint32_t nsp = C.rd_sp_off[r + 1] - C.rd_sp_off[r];
+                const uint32_t nfx = C.rd_fx_off[r + 1] - C.rd_fx_off[r];
+                const uint32_t nsl = C.rd_sl_off[r + 1] - C.rd_sl_off[r];
+                D.rd_sp_grid.push_back(resident_grid(ctx, sym, lds, (nsp + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0));
+                D.rd_fx_grid.push_back(resident_grid(ctx, sym, lds, (nfx + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0));
+                D.rd_sl_grid.push_back(resident_grid(ctx, sym, lds, (nsl + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0));
+            }
         }
         if (bp->plain) {
             // one launch per pair: items of a pair are consecutive, and so
@@ -962,7 +1081,8 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
             ta.queue = D.q_fix;
         } else {
             ta.tk_t = D.sl_t;
-            ta.tk_s = D.sl_t;      // unused by the seal pass
+            ta.tk_s = nullptr;     // every seal runs from the pair's top strip down
+            ta.tk_lo = nullptr;
             ta.nticket = D.nsl;
             ta.queue = D.q_seal;
         }
@@ -983,19 +1103,64 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
     ea.nitems = (uint32_t)b->em_pair_host.size();
     ea.error = b->error;
     if (!b->plain) {
+        // with traceback rounds the pass's fill computes lengths and the
+        // carry words handed between items only
+        const int fwd_mode = b->rounds ? (int)kFillLength : mode;
         for (size_t ci = 0; ci < b->cls.size(); ++ci) {
             const ClassDev &D = b->cls[ci];
             if (!D.nitems) continue;
-            HIP_TRY(launch_fill(D.wpl, mode, fill_args(ci), D.fill_grid, s));
+            HIP_TRY(launch_fill(D.wpl, fwd_mode, fill_args(ci), D.fill_grid, s));
         }
         if (events) HIP_TRY(hipEventRecord(b->ev[2], s));
         if (tb) {
             for (size_t ci = 0; ci < b->cls.size(); ++ci) {
                 const ClassDev &D = b->cls[ci];
                 if (!D.ntb) continue;
-                HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbSpec), D.sp_grid, s));
-                if (D.nfx) HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbFix), D.fx_grid, s));
-                if (D.nsl) HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbSeal), D.sl_grid, s));
+                if (!D.n_rounds) {
+                    HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbSpec), D.sp_grid, s));
+                    if (D.nfx) HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbFix), D.fx_grid, s));
+                    if (D.nsl) HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbSeal), D.sl_grid, s));
+                    continue;
+                }
+                // rounds: refill the round's items with their history in the
+                // round buffer (their carry-in words from the items below are
+                // already stored by the pass's fill), then walk the strips
+                // they hold, from where the earlier rounds left the path
+                for (uint32_t r = 0; r < D.n_rounds; ++r) {
+                    uint32_t *q = D.q_round + (size_t)kQueues * r;
+                    FillArgs fa = fill_args(ci);
+                    fa.item_list = D.rd_items;
+                    fa.item_begin = D.rd_item_off[r];
+                    fa.item_end = D.rd_item_off[r + 1];
+                    fa.it_ck = D.it_rb;
+                    fa.it_cb = D.it_rcb;
+                    fa.out_len = nullptr;
+                    fa.queue = q;
+                    fa.clk = nullptr;
+                    fa.trace = nullptr;
+                    HIP_TRY(launch_fill(D.wpl, kFillTraceback, fa, D.rd_fill_grid[r], s));
+                    TbArgs ta = tb_args(ci, kTbSpec);
+                    ta.it_ck = D.it_rb;
+                    ta.it_cb = D.it_rcb;
+                    ta.tk_t = D.rd_sp_t + D.rd_sp_off[r];
+                    ta.tk_s = D.rd_sp_s + D.rd_sp_off[r];
+                    ta.nticket = D.rd_sp_off[r + 1] - D.rd_sp_off[r];
+                    ta.queue = q + 1;
+                    if (ta.nticket) HIP_TRY(launch_tb(D.wpl, ta, D.rd_sp_grid[r], s));
+                    ta.mode = kTbFix;
+                    ta.tk_t = D.rd_fx_t + D.rd_fx_off[r];
+                    ta.tk_s = D.rd_fx_s + D.rd_fx_off[r];
+                    ta.nticket = D.rd_fx_off[r + 1] - D.rd_fx_off[r];
+                    ta.queue = q + 2;
+                    if (ta.nticket) HIP_TRY(launch_tb(D.wpl, ta, D.rd_fx_grid[r], s));
+                    ta.mode = kTbSeal;
+                    ta.tk_t = D.rd_sl_t + D.rd_sl_off[r];
+                    ta.tk_s = D.rd_sl_top + D.rd_sl_off[r];
+                    ta.tk_lo = D.rd_sl_lo + D.rd_sl_off[r];
+                    ta.nticket = D.rd_sl_off[r + 1] - D.rd_sl_off[r];
+                    ta.queue = q + 3;
+                    if (ta.nticket) HIP_TRY(launch_tb(D.wpl, ta, D.rd_sl_grid[r], s));
+                }
             }
             HIP_TRY(launch_emit(ea, s));
         }
@@ -1030,7 +1195,6 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
                     if (D.pl_sl[k] != 0xffffffffu) {
                         ta = tb_args(ci, kTbSeal);
                         ta.tk_t += D.pl_sl[k];
-                        ta.tk_s += D.pl_sl[k];
                         ta.nticket = 1;
                         ta.queue = ctr + kQueues * k + 3;
                         HIP_TRY(launch_tb(D.wpl, ta, 1, s));
@@ -1234,6 +1398,7 @@ extern "C" lcs_status lcs_batch_info(const lcs_batch *b, lcs_batch_stats *out) {
     if (!b || !out) return LCS_ERR_ARG;
     stats_from_plan(b->plan, b->npairs, out);
     out->device_bytes = b->dev_bytes;
+    out->history_bytes = b->history_bytes;
     out->flags = (int32_t)b->flags;
     return LCS_OK;
 }
@@ -1469,6 +1634,9 @@ extern "C" lcs_status lcs_traceback_batch_noalloc(lcs_ctx *ctx, const lcs_pair *
     hooks.alloc = scratch_alloc;
     hooks.release = scratch_release;
     hooks.user = &use;
+    // a batch whose full traceback history would not fit the array runs in
+    // rounds sized to what its other buffers leave
+    hooks.avail = kNoAllocScratchBytes;
     lcs_batch *b = nullptr;
     st = build_batch(ctx, pairs, count, alphabet, LCS_WANT_TRACEBACK, nullptr, &b, &hooks, true);
     if (st) return st;
@@ -1711,12 +1879,7 @@ static lcs_status plan_only(const uint64_t *m, const uint64_t *n, uint64_t count
     PlanConfig cfg;
     fill_plan_config(cfg, alphabet_size, flags, tuning);
     std::string why = build_plan(shapes, cfg, plan);
-    if (!why.empty()) {
-        if (why.find("longer") != std::string::npos || why.find("too long") != std::string::npos ||
-            why.find("too many") != std::string::npos)
-            return LCS_ERR_TOO_LONG;
-        return LCS_ERR_UNSUPPORTED;
-    }
+    if (!why.empty()) return plan_status(why);
     return LCS_OK;
 }
 

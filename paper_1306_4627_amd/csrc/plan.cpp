@@ -80,6 +80,135 @@ static int auto_batch_wpl(const std::vector<PairShape> &pairs, int sigma) {
     return w < mw ? w : mw;
 }
 
+// History of one item in the round buffer, uint64 words: V checkpoints,
+// then the carry-in words (two per uint64 word).
+static uint64_t item_ck_words(const ClassPlan &C, size_t it, int ckpt) {
+    return ceil_div(C.it_T[it], (uint64_t)ckpt) * (uint64_t)C.wpl * kLanes;
+}
+static uint64_t item_cb_words(const ClassPlan &C, size_t it) {
+    return (C.it_T[it] / kCbitsPer) * kLanes;
+}
+static uint64_t item_round_words(const ClassPlan &C, size_t it, int ckpt) {
+    return item_ck_words(C, it, ckpt) + ceil_div(item_cb_words(C, it), 2);
+}
+
+// Rounds of the traceback (PlanConfig::round_bytes): items are given to
+// rounds chain by chain from the top, as many consecutive items of a chain
+// per round as fit, chains with the most items left first; every round's
+// histories fit round_bytes.  Then each traceback entry's strips are grouped
+// by the round of the items that hold them (strips never straddle items).
+static std::string plan_rounds(const std::vector<PairShape> &pairs, const PlanConfig &cfg, ClassPlan &C) {
+    const size_t nit = C.it_T.size();
+    const uint64_t cap_words = cfg.round_bytes / 8;
+    for (size_t it = 0; it < nit; ++it)
+        if (item_round_words(C, it, cfg.ckpt) > cap_words) return "item history exceeds the round capacity";
+    // chains: [bottom item, top item]
+    std::vector<std::pair<uint32_t, uint32_t>> chains;
+    for (size_t it = 0; it < nit; ++it) {
+        if (C.it_prev[it] < 0) chains.push_back({(uint32_t)it, (uint32_t)it});
+        else chains.back().second = (uint32_t)it;
+    }
+    std::vector<int64_t> next(chains.size());
+    for (size_t c = 0; c < chains.size(); ++c) next[c] = chains[c].second;
+    C.it_round.assign(nit, UINT32_MAX);
+    C.it_rb.assign(nit, 0);
+    C.it_rcb.assign(nit, 0);
+    C.rd_item_off.assign(1, 0);
+    C.rd_items.clear();
+    std::vector<size_t> order(chains.size());
+    std::iota(order.begin(), order.end(), 0);
+    size_t left = nit;
+    uint32_t r = 0;
+    while (left) {
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+            return next[a] - (int64_t)chains[a].first > next[b] - (int64_t)chains[b].first;
+        });
+        uint64_t used = 0;
+        for (size_t c : order) {
+            while (next[c] >= (int64_t)chains[c].first) {
+                const size_t it = (size_t)next[c];
+                const uint64_t w = item_round_words(C, it, cfg.ckpt);
+                if (used + w > cap_words) break;
+                C.it_round[it] = r;
+                C.it_rb[it] = used;
+                C.it_rcb[it] = 2 * (used + item_ck_words(C, it, cfg.ckpt));
+                C.rd_items.push_back((uint32_t)it);
+                used += w;
+                --next[c];
+                --left;
+            }
+        }
+        if (used == 0) return "round scheduling made no progress";
+        C.round_words = std::max(C.round_words, used);
+        C.rd_item_off.push_back((uint32_t)C.rd_items.size());
+        ++r;
+    }
+    C.n_rounds = r;
+    // tickets per round
+    std::vector<std::vector<uint32_t>> sp_t(r), sp_s(r), fx_t(r), fx_s(r), sl_t(r), sl_top(r), sl_lo(r);
+    std::vector<std::vector<uint64_t>> sp_est(r);
+    const uint64_t band = (uint64_t)kLanes * C.wpl;
+    const uint64_t R = (uint64_t)C.strip_bands * band;
+    for (size_t t = 0; t < C.tb_pair.size(); ++t) {
+        const PairShape &ps = pairs[C.tb_pair[t]];
+        const uint64_t nb = ceil_div(ps.m, band);
+        const uint64_t S = ceil_div(nb, (uint64_t)C.strip_bands);
+        auto round_of_band = [&](uint64_t b) {
+            return C.it_round[C.tb_item[t] + (C.tb_lane0[t] + b) / kLanes];
+        };
+        uint64_t s = S;
+        while (s-- > 0) {
+            const uint64_t top = s;
+            const uint32_t rr = round_of_band(top * C.strip_bands);
+            for (uint64_t b = top * C.strip_bands; b < std::min(nb, (top + 1) * C.strip_bands); ++b)
+                if (round_of_band(b) != rr) return "strip straddles two rounds";
+            uint64_t lo = top;
+            while (lo > 0 && round_of_band((lo - 1) * C.strip_bands) == rr) --lo;
+            for (uint64_t q = top + 1; q-- > lo;) {
+                sp_t[rr].push_back((uint32_t)t);
+                sp_s[rr].push_back((uint32_t)q | ((q == top && top + 1 < S) ? kFromAbove : 0u));
+                const uint64_t lo_row = q * R;
+                const uint64_t rows = std::min<uint64_t>(R, ps.m - lo_row);
+                sp_est[rr].push_back(rows + (ps.m ? (uint64_t)((double)ps.n * (double)rows / (double)ps.m) : 0));
+                if (q < top) {
+                    fx_t[rr].push_back((uint32_t)t);
+                    fx_s[rr].push_back((uint32_t)q);
+                }
+            }
+            if (top > lo) {
+                sl_t[rr].push_back((uint32_t)t);
+                sl_top[rr].push_back((uint32_t)top);
+                sl_lo[rr].push_back((uint32_t)lo);
+            }
+            s = lo;
+        }
+    }
+    C.rd_sp_off.assign(1, 0);
+    C.rd_fx_off.assign(1, 0);
+    C.rd_sl_off.assign(1, 0);
+    C.rd_sp_t.clear(); C.rd_sp_s.clear(); C.rd_fx_t.clear(); C.rd_fx_s.clear();
+    C.rd_sl_t.clear(); C.rd_sl_top.clear(); C.rd_sl_lo.clear();
+    for (uint32_t q = 0; q < r; ++q) {
+        // speculative strips longest walk first within the round
+        std::vector<size_t> o(sp_t[q].size());
+        std::iota(o.begin(), o.end(), 0);
+        std::stable_sort(o.begin(), o.end(), [&](size_t x, size_t y) { return sp_est[q][x] > sp_est[q][y]; });
+        for (size_t k : o) {
+            C.rd_sp_t.push_back(sp_t[q][k]);
+            C.rd_sp_s.push_back(sp_s[q][k]);
+        }
+        C.rd_fx_t.insert(C.rd_fx_t.end(), fx_t[q].begin(), fx_t[q].end());
+        C.rd_fx_s.insert(C.rd_fx_s.end(), fx_s[q].begin(), fx_s[q].end());
+        C.rd_sl_t.insert(C.rd_sl_t.end(), sl_t[q].begin(), sl_t[q].end());
+        C.rd_sl_top.insert(C.rd_sl_top.end(), sl_top[q].begin(), sl_top[q].end());
+        C.rd_sl_lo.insert(C.rd_sl_lo.end(), sl_lo[q].begin(), sl_lo[q].end());
+        C.rd_sp_off.push_back((uint32_t)C.rd_sp_t.size());
+        C.rd_fx_off.push_back((uint32_t)C.rd_fx_t.size());
+        C.rd_sl_off.push_back((uint32_t)C.rd_sl_t.size());
+    }
+    return std::string();
+}
+
 std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cfg, Plan &out) {
     out = Plan();
     out.cfg = cfg;
@@ -87,6 +216,8 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
         return "words_per_lane must be 1, 2, 4 or 8";
     if (cfg.traceback && cfg.ckpt != 64 && cfg.ckpt != 128 && cfg.ckpt != 256)
         return "ckpt_interval must be 64, 128 or 256";
+    if (cfg.round_bytes && (!cfg.traceback || cfg.plain || cfg.link_items > 1))
+        return "traceback rounds need a packed traceback batch without linked items";
     const size_t np = pairs.size();
     out.pair_class.assign(np, UINT32_MAX);
 
@@ -280,6 +411,13 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
             const uint64_t band = (uint64_t)kLanes * wpl;
             const uint64_t rows = std::max<uint64_t>((uint64_t)std::max(cfg.strip_rows, 1), band);
             C.strip_bands = (uint32_t)ceil_div(rows, band);
+            if (cfg.round_bytes) {
+                // rounds refill whole items: a strip must not straddle an
+                // item boundary, so its band count divides the 64 of an item
+                uint32_t sb = 1;
+                while (sb < C.strip_bands && sb < (uint32_t)kLanes) sb *= 2;
+                C.strip_bands = sb;
+            }
             for (size_t t = 0; t < C.tb_pair.size(); ++t) {
                 const uint64_t nb = ceil_div(pairs[C.tb_pair[t]].m, band);
                 const uint64_t S = ceil_div(nb, (uint64_t)C.strip_bands);
@@ -323,6 +461,10 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
                 }
                 C.sp_t.swap(st);
                 C.sp_s.swap(ss);
+            }
+            if (cfg.round_bytes) {
+                std::string why = plan_rounds(pairs, cfg, C);
+                if (!why.empty()) return why;
             }
         }
         out.items += nit;
@@ -540,6 +682,88 @@ std::string check_plan(const std::vector<PairShape> &pairs, const Plan &p) {
         if (C.sl_t.size() != nseal) return "seal tickets";
         for (size_t k = 0; k < C.sl_t.size(); ++k)
             if (C.sl_t[k] >= nt || seen_sp[C.sl_t[k]].size() < 2) return "seal ticket";
+        if (!p.cfg.round_bytes) continue;
+        // rounds: every item refilled in exactly one round, within the round
+        // capacity, its history inside the round buffer and apart from the
+        // other items of its round; chains top-down
+        const size_t nit = C.it_T.size();
+        const uint32_t R = C.n_rounds;
+        if (C.it_round.size() != nit || C.it_rb.size() != nit || C.rd_item_off.size() != R + 1 ||
+            C.rd_sp_off.size() != R + 1 || C.rd_fx_off.size() != R + 1 || C.rd_sl_off.size() != R + 1)
+            return "round table sizes";
+        std::vector<int> refills(nit, 0);
+        for (uint32_t r = 0; r < R; ++r) {
+            std::vector<std::pair<uint64_t, uint64_t>> iv;
+            uint64_t used = 0;
+            for (uint32_t k = C.rd_item_off[r]; k < C.rd_item_off[r + 1]; ++k) {
+                const uint32_t it = C.rd_items[k];
+                if (it >= nit || C.it_round[it] != r) return "round item";
+                if (C.it_rcb[it] != 2 * (C.it_rb[it] + item_ck_words(C, it, p.cfg.ckpt)))
+                    return "round carry-word offset";
+                ++refills[it];
+                const uint64_t w = item_round_words(C, it, p.cfg.ckpt);
+                iv.push_back({C.it_rb[it], C.it_rb[it] + w});
+                used += w;
+            }
+            if (used * 8 > p.cfg.round_bytes || used > C.round_words) return "round over capacity";
+            std::sort(iv.begin(), iv.end());
+            for (size_t k = 0; k < iv.size(); ++k) {
+                if (iv[k].second > C.round_words) return "item history beyond the round buffer";
+                if (k && iv[k].first < iv[k - 1].second) return "item histories overlap";
+            }
+        }
+        for (size_t it = 0; it < nit; ++it) {
+            if (refills[it] != 1) return "item not refilled exactly once";
+            if (C.it_prev[it] >= 0 && C.it_round[it - 1] < C.it_round[it])
+                return "chain item refilled before the item above it";
+        }
+        // every strip walked speculatively once, in the round of its items;
+        // group tops below a pair's top strip start from the strip above;
+        // fix-ups for every other strip of a group; one seal per group of
+        // two or more strips
+        std::vector<std::vector<int>> sp2(nt), fx2(nt), top_of(nt);
+        for (size_t t = 0; t < nt; ++t) {
+            sp2[t].assign(seen_sp[t].size(), 0);
+            fx2[t].assign(seen_sp[t].size(), 0);
+            top_of[t].assign(seen_sp[t].size(), -1);
+        }
+        auto strip_round = [&](size_t t, uint64_t s) {
+            return C.it_round[C.tb_item[t] + (C.tb_lane0[t] + s * C.strip_bands) / kLanes];
+        };
+        for (uint32_t r = 0; r < R; ++r) {
+            for (uint32_t k = C.rd_sp_off[r]; k < C.rd_sp_off[r + 1]; ++k) {
+                const uint32_t t = C.rd_sp_t[k], sv = C.rd_sp_s[k] & ~kFromAbove;
+                if (t >= nt || sv >= sp2[t].size()) return "round speculative ticket range";
+                if (strip_round(t, sv) != r) return "strip walked in another round";
+                ++sp2[t][sv];
+                const bool above = (C.rd_sp_s[k] & kFromAbove) != 0;
+                const bool group_top = sv + 1 == sp2[t].size() || strip_round(t, sv + 1) != r;
+                if (above != (group_top && sv + 1 < sp2[t].size())) return "round start flag";
+            }
+            for (uint32_t k = C.rd_fx_off[r]; k < C.rd_fx_off[r + 1]; ++k) {
+                const uint32_t t = C.rd_fx_t[k], sv = C.rd_fx_s[k];
+                if (t >= nt || sv + 1 >= fx2[t].size()) return "round fix-up ticket range";
+                if (strip_round(t, sv) != r || strip_round(t, sv + 1) != r) return "fix-up across rounds";
+                ++fx2[t][sv];
+            }
+            for (uint32_t k = C.rd_sl_off[r]; k < C.rd_sl_off[r + 1]; ++k) {
+                const uint32_t t = C.rd_sl_t[k], top = C.rd_sl_top[k], lo = C.rd_sl_lo[k];
+                if (t >= nt || top >= sp2[t].size() || lo >= top) return "round seal ticket range";
+                if (strip_round(t, top) != r || strip_round(t, lo) != r) return "seal across rounds";
+                if (top + 1 < sp2[t].size() && strip_round(t, top + 1) == r) return "seal below a group top";
+                if (lo > 0 && strip_round(t, lo - 1) == r) return "seal above a group bottom";
+                for (uint32_t q = lo; q <= top; ++q)
+                    if (top_of[t][q]++ != -1) return "strip sealed twice";
+            }
+        }
+        for (size_t t = 0; t < nt; ++t)
+            for (size_t q = 0; q < sp2[t].size(); ++q) {
+                if (sp2[t][q] != 1) return "strip not walked once in the rounds";
+                const bool group_top = q + 1 == sp2[t].size() || strip_round(t, q + 1) != strip_round(t, q);
+                if (fx2[t][q] != (group_top ? 0 : 1)) return "round fix-ups";
+                const bool single = group_top && (q == 0 || strip_round(t, q - 1) != strip_round(t, q));
+                if ((top_of[t][q] == -1) != single) return "round seals";
+            }
     }
     // regions do not overlap
     std::vector<std::pair<uint64_t, uint64_t>> iv;

@@ -45,6 +45,12 @@ struct PlanConfig {
     bool plain = false;     // one pair per item, no packing
     int strip_rows = 4096;  // rows per traceback strip (rounded up to whole bands)
     int link_items = 1;     // items one run of linked chains may span (1 = no sharing)
+    // Traceback in rounds (0 = one pass with every item's history stored at
+    // once): the fill runs once for lengths and carry hand-over words only,
+    // then the items are refilled round by round, each round storing the
+    // history of a set of items in one shared buffer of at most round_bytes
+    // and walking the strips those items hold (see ClassPlan's rd_* tables).
+    uint64_t round_bytes = 0;
 };
 
 // A chain may start in the free lanes of the item before it when its step
@@ -88,7 +94,31 @@ struct ClassPlan {
     uint64_t n_bands = 0, n_strips = 0;
     uint64_t ck_words = 0, cb_words = 0, xf_words = 0;
     uint64_t lane_steps = 0;
+    // Traceback in rounds (PlanConfig::round_bytes > 0).  Every item belongs
+    // to one round; a chain's items are taken top-down, so the round of an
+    // item is never earlier than that of the item above it in its chain, and
+    // the strips a round walks continue the path the earlier rounds wrote.
+    // Per item: its round and the offset of its history in the round buffer
+    // (uint64 units; V checkpoints first, then the carry-in words, so the
+    // carry words of the item start at 2 * (it_rb + checkpoint words) in
+    // uint32 units).  Per round r, entries [off[r], off[r+1]) of: the items
+    // to refill; the speculative tickets (entry, strip; bit 31 of the strip
+    // set when the strip is the top of its group below the pair's top strip
+    // and starts from the column the walk left the strip above); the fix-up
+    // tickets (entry, strip); the seal tickets (entry, top strip of the
+    // group, bottom strip of the group).
+    uint32_t n_rounds = 0;
+    uint64_t round_words = 0;             // uint64 words of the round buffer
+    std::vector<uint32_t> it_round;
+    std::vector<uint64_t> it_rb;          // checkpoints (uint64 units)
+    std::vector<uint64_t> it_rcb;         // carry-in words (uint32 units, same buffer)
+    std::vector<uint32_t> rd_item_off, rd_items;
+    std::vector<uint32_t> rd_sp_off, rd_sp_t, rd_sp_s;
+    std::vector<uint32_t> rd_fx_off, rd_fx_t, rd_fx_s;
+    std::vector<uint32_t> rd_sl_off, rd_sl_t, rd_sl_top, rd_sl_lo;
 };
+
+constexpr uint32_t kFromAbove = 0x80000000u;   // speculative ticket flag (rounds)
 
 // One region of the Y stream: the pair's Y codes at columns 0..n-1 and the
 // sentinel code elsewhere, each element scaled to a byte offset into the

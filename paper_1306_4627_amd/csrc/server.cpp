@@ -285,6 +285,11 @@ void lcs_server::run() {
         hooks.alloc = arena_alloc;
         hooks.release = arena_release;
         hooks.user = this;
+        // a lone traceback request whose full history would not fit even the
+        // empty arena runs in rounds sized to it (one that fits waits for
+        // memory instead, and a group that does not fit is split: rounds
+        // cost a second fill)
+        hooks.avail = group.size() == 1 ? arena_bytes : 0;
         lcs_tuning tun{};
         (void)lcs::tuning_cached(ctx, pairs.data(), pairs.size(), h.alpha_size, flags, &tun);
         lcs_batch *b = nullptr;

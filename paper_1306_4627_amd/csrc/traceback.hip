@@ -10,6 +10,7 @@
 // the traceback recomputes only the tiles the path crosses.
 #include "kernels.hpp"
 #include "bitvec.hpp"
+#include "plan.hpp"
 
 namespace lcs {
 
@@ -148,9 +149,15 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
         uint32_t *cross = a.cross + a.tb_band0[te];
         uint32_t *sres = a.strip_res + 2 * (size_t)a.tb_strip0[te];
         const int32_t S = (int32_t)((m + (uint32_t)R - 1) / (uint32_t)R);
-        int32_t s = a.mode == kTbSeal ? S - 2 : (int32_t)a.tk_s[ticket];
+        // the seal pass runs down a group of strips: the pair's strips, or in
+        // traceback rounds the strips of one round
+        const bool seal = a.mode == kTbSeal;
+        const int32_t s_top = seal && a.tk_s ? (int32_t)a.tk_s[ticket] : S - 1;
+        const int32_t s_lo = seal && a.tk_lo ? (int32_t)a.tk_lo[ticket] : 0;
+        const bool from_above = !seal && (a.tk_s[ticket] & kFromAbove) != 0;
+        int32_t s = seal ? s_top - 1 : (int32_t)(a.tk_s[ticket] & ~kFromAbove);
         // seal: exit column of the strip above the current one
-        int32_t e = a.mode == kTbSeal ? (int32_t)cross[(S - 1) * G] : 0;
+        int32_t e = seal ? (int32_t)cross[s_top * G] : 0;
 
         for (;;) {
             const int32_t top = (s + 1) * R;       // first row above strip s
@@ -168,6 +175,9 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
                 if (s == S - 1) {
                     i = (int32_t)m;
                     j = (int32_t)n;
+                } else if (from_above) {
+                    // the path above this strip is final (an earlier round)
+                    j = (int32_t)cross[(s + 1) * G];
                 } else {
                     j = guess;
                 }
@@ -496,7 +506,7 @@ __global__ __launch_bounds__(kTbBlock) void k_traceback(TbArgs a) {
                 // that path does
                 e = !walk ? (int32_t)sres[2 * s + 1] : merged ? (int32_t)cross[s * G] : j;
             }
-            if (a.mode != kTbSeal || s == 0) break;
+            if (a.mode != kTbSeal || s == s_lo) break;
             --s;
         }
     }

@@ -65,7 +65,8 @@ class lcs_tuning(ctypes.Structure):
     _fields_ = [("words_per_lane", ctypes.c_int32), ("ckpt_interval", ctypes.c_int32),
                 ("persistent_waves", ctypes.c_int32), ("plain", ctypes.c_int32),
                 ("strip_rows", ctypes.c_int32), ("tb_tiles", ctypes.c_int32),
-                ("tb_bands", ctypes.c_int32), ("link_items", ctypes.c_int32)]
+                ("tb_bands", ctypes.c_int32), ("link_items", ctypes.c_int32),
+                ("tb_round_kib", ctypes.c_int32)]
 
 
 class lcs_server_config(ctypes.Structure):
@@ -88,7 +89,9 @@ class lcs_batch_stats(ctypes.Structure):
                 ("groups", ctypes.c_uint64), ("lanes", ctypes.c_uint64),
                 ("lane_steps", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
                 ("words_per_lane", ctypes.c_int32), ("ckpt_interval", ctypes.c_int32),
-                ("classes", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("classes", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("tb_rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("history_bytes", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -254,9 +257,10 @@ def _alpha(a) -> Alphabet:
 
 
 def _tuning(words_per_lane=0, ckpt_interval=0, persistent_waves=0, plain=False, strip_rows=0,
-            tb_tiles=0, tb_bands=0, link_items=0):
+            tb_tiles=0, tb_bands=0, link_items=0, tb_round_kib=0):
     return lcs_tuning(int(words_per_lane), int(ckpt_interval), int(persistent_waves), int(bool(plain)),
-                      int(strip_rows), int(tb_tiles), int(tb_bands), int(link_items))
+                      int(strip_rows), int(tb_tiles), int(tb_bands), int(link_items),
+                      int(tb_round_kib))
 
 
 class _Pairs:
@@ -411,7 +415,7 @@ class Batch:
                  graph: bool = False, words_per_lane: int = 0, ckpt_interval: int = 0,
                  persistent_waves: int = 0, plain: bool = False, strip_rows: int = 0,
                  tb_tiles: int = 0, tb_bands: int = 0, threshold: Optional[float] = None,
-                 link_items: int = 0, fill_trace: bool = False):
+                 link_items: int = 0, fill_trace: bool = False, tb_round_kib: int = 0):
         self.ctx = ctx
         self._pairs = _Pairs(pairs)
         self.count = self._pairs.count
@@ -424,7 +428,7 @@ class Batch:
         if fill_trace:
             flags |= LCS_FILL_TRACE
         t = _tuning(words_per_lane, ckpt_interval, persistent_waves, plain, strip_rows, tb_tiles,
-                    tb_bands, link_items)
+                    tb_bands, link_items, tb_round_kib)
         h = ctypes.c_void_p()
         _check(_lib.lcs_batch_create(ctx.h, self._pairs.ptr(), self.count,
                                      ctypes.byref(self._alpha.c), flags, ctypes.byref(t),

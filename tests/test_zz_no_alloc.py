@@ -86,3 +86,21 @@ def test_noalloc_refuses_batches_beyond_the_array(ctx, lcs):
     pairs = _related_pairs(g, 5, 1, 400, inputs.DNA)
     _say("noalloc after refusal")
     assert lcs.lcs_traceback_batch_noalloc(ctx, pairs, "dna") == lcs.lcs_traceback_batch(ctx, pairs, "dna")
+
+
+def test_noalloc_history_beyond_the_array_runs_in_rounds(ctx, lcs):
+    # one 150000-row pair: about 90 MB of full traceback history, more than
+    # the array holds, so the allocation-free call plans rounds; then a
+    # smaller call again
+    g = inputs.rng(7102)
+    x = inputs.random_seq(g, 150000, inputs.DNA)
+    y, _ = inputs.mutate(g, x, 0.12, inputs.DNA)
+    full = lcs.plan_describe([x.size], [y.size], 4, traceback=True)
+    assert full["history_bytes"] > lcs.noalloc_scratch_bytes()
+    _say("noalloc in rounds: 150000 x 150000")
+    got = lcs.lcs_traceback_batch_noalloc(ctx, [(x, y)], "dna")
+    want = lcs.lcs_traceback_batch(ctx, [(x, y)], "dna")
+    assert got == want
+    pairs = _related_pairs(g, 6, 1, 900, inputs.DNA)
+    _say("noalloc after rounds")
+    assert lcs.lcs_traceback_batch_noalloc(ctx, pairs, "dna") == lcs.lcs_traceback_batch(ctx, pairs, "dna")
