@@ -190,6 +190,11 @@ void lcs_destroy(lcs_ctx *ctx);
  * NULL selects the context's own stream.  The caller keeps the stream alive. */
 lcs_status lcs_set_stream(lcs_ctx *ctx, void *hip_stream);
 
+/* The context's device as the runtime reports it: compute units and peak
+ * shader clock in kHz (either pointer may be NULL).  The roofline of the
+ * fill is compute_units * 64 lanes * clock * 64 cells / 6 instructions. */
+lcs_status lcs_device_info(lcs_ctx *ctx, int32_t *compute_units, int32_t *peak_clock_khz);
+
 /* Wait for all work queued on the context's stream. */
 lcs_status lcs_synchronize(lcs_ctx *ctx);
 

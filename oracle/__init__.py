@@ -6,6 +6,7 @@ calls it.
 """
 from .oracle import (  # noqa: F401
     build_oracle,
+    use_native_build,
     lcs_length,
     lcs_traceback,
     lcs_traceback_ckpt,

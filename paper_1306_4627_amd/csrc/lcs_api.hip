@@ -43,6 +43,7 @@ struct lcs_ctx {
     size_t budget = 0;
     size_t in_use = 0;
     int num_cus = 0;
+    int clock_khz = 0;      // peak shader clock the device reports
     std::string arch;
     std::map<TuneKey, std::pair<lcs_tuning, float>> tune_cache;   // autotuner results
     std::map<std::tuple<const void *, int, size_t>, int> occupancy;   // kernel, block, LDS -> groups per CU
@@ -387,6 +388,7 @@ extern "C" lcs_status lcs_create(lcs_ctx **out, int device, size_t mem_budget_by
     if (!c) return LCS_ERR_NOMEM;
     c->device = device;
     c->num_cus = prop.multiProcessorCount;
+    c->clock_khz = prop.clockRate;
     c->arch = prop.gcnArchName;
     HIP_TRY(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
     c->stream = c->own_stream;
@@ -410,6 +412,13 @@ extern "C" void lcs_destroy(lcs_ctx *ctx) {
         (void)hipStreamDestroy(ctx->own_stream);
     }
     delete ctx;
+}
+
+extern "C" lcs_status lcs_device_info(lcs_ctx *ctx, int32_t *compute_units, int32_t *peak_clock_khz) {
+    if (!ctx) return LCS_ERR_ARG;
+    if (compute_units) *compute_units = ctx->num_cus;
+    if (peak_clock_khz) *peak_clock_khz = ctx->clock_khz;
+    return LCS_OK;
 }
 
 extern "C" lcs_status lcs_set_stream(lcs_ctx *ctx, void *hip_stream) {
@@ -694,6 +703,7 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     b->out_bytes = (flags & LCS_WANT_TRACEBACK) ? oo : 0;
     PlanConfig cfg;
     fill_plan_config(cfg, sigma, flags, tuning);
+    cfg.cus = ctx->num_cus;
     if (max_wpl(sigma) == 0) return LCS_ERR_UNSUPPORTED;
     if (cfg.wpl && !wpl_fits(sigma, cfg.wpl)) return LCS_ERR_UNSUPPORTED;
     std::string why = build_plan(shapes, cfg, b->plan);

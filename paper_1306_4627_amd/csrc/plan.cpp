@@ -58,15 +58,14 @@ int max_wpl(int sigma) {
 
 // One words-per-lane for the whole batch (one fill launch).  When every
 // lane of the batch at one word per lane fits the GPU's resident wave slots
-// at once (256 CUs x 16 waves x 64 lanes), the fill is bound by the latency
+// at once (compute units x 16 waves x 64 lanes), the fill is bound by the latency
 // of a step, which grows with the words in a lane's carry chain: one word
 // (a single 262144-row pair: 12.0 ms against 15.0 at two words).
 // Otherwise two words per lane once most of the cells belong to pairs
 // longer than 16 words (the per-step overhead is then spread over 128
 // rows), one word otherwise (short columns keep more lanes busy).
-constexpr uint64_t kResidentLanes = 256ull * 16 * 64;
-
-static int auto_batch_wpl(const std::vector<PairShape> &pairs, int sigma) {
+static int auto_batch_wpl(const std::vector<PairShape> &pairs, int sigma, int cus) {
+    const uint64_t resident_lanes = (uint64_t)std::max(cus, 1) * 16 * kLanes;
     double big = 0, all = 0;
     uint64_t lanes1 = 0;
     for (const PairShape &p : pairs) {
@@ -75,7 +74,7 @@ static int auto_batch_wpl(const std::vector<PairShape> &pairs, int sigma) {
         if ((p.m + 63) / 64 > 16) big += c;
         if (p.n) lanes1 += (p.m + 63) / 64;
     }
-    int w = (all > 0 && big >= 0.5 * all && lanes1 > kResidentLanes) ? 2 : 1;
+    int w = (all > 0 && big >= 0.5 * all && lanes1 > resident_lanes) ? 2 : 1;
     int mw = max_wpl(sigma);
     return w < mw ? w : mw;
 }
@@ -221,7 +220,7 @@ std::string build_plan(const std::vector<PairShape> &pairs, const PlanConfig &cf
     const size_t np = pairs.size();
     out.pair_class.assign(np, UINT32_MAX);
 
-    const int batch_wpl = cfg.wpl ? cfg.wpl : auto_batch_wpl(pairs, cfg.sigma);
+    const int batch_wpl = cfg.wpl ? cfg.wpl : auto_batch_wpl(pairs, cfg.sigma, cfg.cus);
     // assign pairs to classes by words-per-lane
     int class_of_wpl[9];
     for (int &c : class_of_wpl) c = -1;

@@ -51,6 +51,7 @@ struct PlanConfig {
     // history of a set of items in one shared buffer of at most round_bytes
     // and walking the strips those items hold (see ClassPlan's rd_* tables).
     uint64_t round_bytes = 0;
+    int cus = 256;          // compute units of the device (resident wave slots)
 };
 
 // A chain may start in the free lanes of the item before it when its step

@@ -123,6 +123,8 @@ def _load() -> ctypes.CDLL:
     lib.lcs_create.restype = i32
     lib.lcs_destroy.argtypes = [vp]
     lib.lcs_destroy.restype = None
+    lib.lcs_device_info.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int32)]
+    lib.lcs_device_info.restype = i32
     lib.lcs_set_stream.argtypes = [vp, vp]
     lib.lcs_set_stream.restype = i32
     lib.lcs_synchronize.argtypes = [vp]
@@ -303,6 +305,12 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def device_info(self) -> dict:
+        """Compute units and peak shader clock (kHz) of the context's device."""
+        cu, clk = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(_lib.lcs_device_info(self.h, ctypes.byref(cu), ctypes.byref(clk)), "lcs_device_info")
+        return {"compute_units": int(cu.value), "peak_clock_khz": int(clk.value)}
 
     def set_stream(self, stream) -> None:
         """Use a HIP stream: an int handle, a ``torch.cuda.Stream`` or None."""
