@@ -7,6 +7,8 @@
 // needs it: the carry hand-over is a shift of the wave's carry-out lane mask
 // (ballot) by one lane, fed back as the carry-in lane mask of the next step.
 // No cross-lane add is ever waited for inside a step.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "bitvec.hpp"
 #include "plan.hpp"
@@ -32,79 +34,83 @@ __device__ __forceinline__ void load16(const uint16_t *ys, uint32_t t0, uint32_t
     for (int e = 0; e < 8; ++e) d[e] = (uint32_t)p[2 * e] | ((uint32_t)p[2 * e + 1] << 16);
 }
 
-#ifndef LCS_FILL_HOIST
-#define LCS_FILL_HOIST 8
-#endif
+// Match masks of eight steps (steps s0..s0+7 of a group of sixteen stream
+// values): they depend on the stream only, so they are read from LDS ahead
+// of the column steps that use them.
+template <int WPL, bool RAW>
+__device__ __forceinline__ void read_masks8(const uint32_t (&Yg)[8], int s0, const char *lanecol,
+                                            uint64_t (&M)[8][WPL]) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int s = s0 + e;
+        const uint32_t y2 = Yg[s >> 1];
+        uint32_t off = (s & 1) ? (y2 >> 16) : (y2 & 0xffffu);
+        if (RAW) off <<= 9 + (WPL == 1 ? 0 : WPL == 2 ? 1 : WPL == 4 ? 2 : 3);
+        const char *row = lanecol + off;
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) M[e][q] = *(const uint64_t *)(row + q * 512);
+    }
+}
 
-// Sixteen column steps t..t+15 of one lane.  The carry-in lane mask of a
-// step is the carry-out mask of the previous step shifted up by one lane,
-// with segment starts cleared.  With CHAIN, lane 0 takes the hand-over bit
-// of the feeding item and lane 63's carry-out is collected for the next
-// item: one scalar add-with-carry chain shifts the mask (2 * mask, the carry
-// into the low word being the next step's hand-over bit, selected by
-// s_bitcmp1 from `innext`, bit s = the bit of step s+1) and lane 63's carry
-// (bit 63 of the mask) is shifted into `ow` (most recent step in bit 0): with
-// OWASM by the same chain's carry out, else by plain code the compiler
-// schedules.  Which is faster depends on the mode and width (the plain form
-// leaves the lengths-only fill many SGPRs to spill into VGPR lanes, which at
-// two words per lane it still hides, at one word per lane and in the other
-// modes not), so the kernel picks per instantiation.  With TB, every lane's carry-in bits are accumulated (newest in bit 0:
-// acc = 2 * acc + carry-in, one v_addc_co_u32 with the mask as carry-in) and
-// stored every 32 steps.
-template <int WPL, bool TB, bool CHAIN, bool RAW, bool OWASM>
+// Eight column steps t+8h..t+8h+7 of one lane, with their match masks.  The
+// carry-in lane mask of a step is the carry-out mask of the previous step
+// shifted up by one lane, with segment starts cleared.  With CHAIN, lane 0
+// takes the hand-over bit of the feeding item and lane 63's carry-out is
+// collected for the next item: one scalar add-with-carry chain shifts the
+// mask (2 * mask, the carry into the low word being the next step's hand-over
+// bit, selected by s_bitcmp1 from `innext`, bit s = the bit of step s+1) and
+// shifts lane 63's carry (bit 63 of the mask, the chain's carry out) into
+// `ow` (most recent step in bit 0).  (Collected by plain code instead, the
+// lengths-only fill at two words per lane spilled some 100 SGPRs into VGPR
+// lanes and had its match-mask reads sunk next to their steps.)  With TB,
+// every lane's carry-in bits are accumulated (newest in bit 0: acc = 2 * acc
+// + carry-in, one v_addc_co_u32 with the mask as carry-in) and stored every
+// 32 steps.
+template <int WPL, bool TB, bool CHAIN>
+__device__ __forceinline__ void steps8(const uint64_t (&Mg)[8][WPL], int h, uint32_t t,
+                                       uint64_t notstart, uint64_t &cmask, uint32_t &acc,
+                                       uint32_t *cbp, uint32_t (&vlo)[WPL], uint32_t (&vhi)[WPL],
+                                       uint32_t innext, uint32_t &ow) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        uint64_t cm = cmask;
+        if (TB) {
+            asm("v_addc_co_u32 %[a], vcc, %[a], %[a], %[m]" : [a] "+v"(acc) : [m] "s"(cm) : "vcc");
+            if (h * 8 + e == 15 && (t & 16u)) cbp[(size_t)((t + 15) >> 5) * 64] = acc;
+        }
+        column_step<WPL>(vlo, vhi, Mg[e], cm);
+        if (CHAIN) {
+            const uint32_t clo = (uint32_t)cm, chi = (uint32_t)(cm >> 32);
+            uint32_t lo, hi;
+            asm("s_bitcmp1_b32 %[in], %[bit]\n\t"
+                "s_addc_u32 %[lo], %[clo], %[clo]\n\t"
+                "s_addc_u32 %[hi], %[chi], %[chi]\n\t"
+                "s_addc_u32 %[ow], %[ow], %[ow]"
+                : [lo] "=&s"(lo), [hi] "=&s"(hi), [ow] "+s"(ow)
+                : [in] "s"(innext), [bit] "i"(h * 8 + e), [clo] "s"(clo), [chi] "s"(chi)
+                : "scc");
+            cmask = (((uint64_t)hi << 32) | lo) & notstart;
+        } else {
+            cmask = (cm << 1) & notstart;
+        }
+    }
+}
+
+// Sixteen column steps t..t+15 of one lane, the match masks of each eight
+// steps read just before them.
+template <int WPL, bool TB, bool CHAIN, bool RAW>
 __device__ __forceinline__ void run16(const uint32_t (&Yg)[8], uint32_t t, const char *lanecol,
                                       uint64_t notstart, uint64_t &cmask, uint32_t &acc,
                                       uint32_t *cbp, uint32_t (&vlo)[WPL], uint32_t (&vhi)[WPL],
                                       uint32_t innext, uint32_t &ow) {
-    constexpr int H = LCS_FILL_HOIST;   // steps whose match masks are read together
 #pragma unroll
-    for (int h = 0; h < 16 / H; ++h) {
-        // the match masks of H steps are read up front: they depend on the
-        // stream only, so their LDS latency overlaps the column steps
-        uint64_t Mg[H][WPL];
-#pragma unroll
-        for (int e = 0; e < H; ++e) {
-            const int s = h * H + e;
-            const uint32_t y2 = Yg[s >> 1];
-            uint32_t off = (s & 1) ? (y2 >> 16) : (y2 & 0xffffu);
-            if (RAW) off <<= 9 + (WPL == 1 ? 0 : WPL == 2 ? 1 : WPL == 4 ? 2 : 3);
-            const char *row = lanecol + off;
-#pragma unroll
-            for (int q = 0; q < WPL; ++q) Mg[e][q] = *(const uint64_t *)(row + q * 512);
-        }
-#pragma unroll
-        for (int e = 0; e < H; ++e) {
-            uint64_t cm = cmask;
-            if (TB) {
-                asm("v_addc_co_u32 %[a], vcc, %[a], %[a], %[m]" : [a] "+v"(acc) : [m] "s"(cm) : "vcc");
-                if (h * H + e == 15 && (t & 16u)) cbp[(size_t)((t + 15) >> 5) * 64] = acc;
-            }
-            column_step<WPL>(vlo, vhi, Mg[e], cm);
-            if (CHAIN) {
-                const uint32_t clo = (uint32_t)cm, chi = (uint32_t)(cm >> 32);
-                uint32_t lo, hi;
-                if (OWASM) {
-                    asm("s_bitcmp1_b32 %[in], %[bit]\n\t"
-                        "s_addc_u32 %[lo], %[clo], %[clo]\n\t"
-                        "s_addc_u32 %[hi], %[chi], %[chi]\n\t"
-                        "s_addc_u32 %[ow], %[ow], %[ow]"
-                        : [lo] "=&s"(lo), [hi] "=&s"(hi), [ow] "+s"(ow)
-                        : [in] "s"(innext), [bit] "i"(h * H + e), [clo] "s"(clo), [chi] "s"(chi)
-                        : "scc");
-                } else {
-                    asm("s_bitcmp1_b32 %[in], %[bit]\n\t"
-                        "s_addc_u32 %[lo], %[clo], %[clo]\n\t"
-                        "s_addc_u32 %[hi], %[chi], %[chi]"
-                        : [lo] "=&s"(lo), [hi] "=&s"(hi)
-                        : [in] "s"(innext), [bit] "i"(h * H + e), [clo] "s"(clo), [chi] "s"(chi)
-                        : "scc");
-                    ow = (ow << 1) | (chi >> 31);
-                }
-                cmask = (((uint64_t)hi << 32) | lo) & notstart;
-            } else {
-                cmask = (cm << 1) & notstart;
-            }
-        }
+    for (int h = 0; h < 2; ++h) {
+        uint64_t Mg[8][WPL];
+        read_masks8<WPL, RAW>(Yg, 8 * h, lanecol, Mg);
+        // (without this barrier the scheduler may sink each read to its
+        // step, and every step then waits out a whole LDS latency)
+        __builtin_amdgcn_sched_barrier(0);
+        steps8<WPL, TB, CHAIN>(Mg, h, t, notstart, cmask, acc, cbp, vlo, vhi, innext, ow);
         // keep the scheduler from spreading the scalar work of many steps
         // across each other (it would hold dozens of masks live)
         __builtin_amdgcn_sched_barrier(0);
@@ -171,13 +177,6 @@ template <int WPL, int MODE, bool RAW>
 __device__ __forceinline__ void fill_body(const FillArgs &a) {
     constexpr bool TB = MODE == kFillTraceback;
     constexpr bool THR = MODE == kFillThreshold;
-    // lane 63's carries collected in the scalar chain itself, except in the
-    // lengths-only fill at two or more words per lane (interleaved timings:
-    // 4096-pair related batch, lengths only at two words: 5.82 ms plain vs
-    // 6.63 ms; threshold pass at two words: 5.86 vs 5.07 ms; 65536 short
-    // pairs at one word: 0.229 vs 0.217 ms; one long pair at one word: 47.6
-    // vs 44.2 ns per step)
-    constexpr bool OWASM = TB || THR || WPL == 1;
     extern __shared__ uint64_t smem[];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -235,32 +234,29 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
         if (pair >= 0) {
             m = a.pair_m[pair];
             const uint8_t *xc = a.xcodes + a.pair_xoff[pair];
+#pragma unroll
             for (int q = 0; q < WPL; ++q) {
                 const uint32_t row0 = (word0 + q) * 64u;
-                if (row0 >= m) break;
-                uint64_t *col = pm + q * 64 + lane;
-                const uint32_t cnt = (m - row0) < 64u ? (m - row0) : 64u;
+                if (row0 >= m) continue;
                 // the word's 64 codes with four 16-byte loads issued together
                 // (each sequence starts 64-byte aligned in the X arena and is
                 // padded to a multiple of 64 bytes)
-                // (walked with a run-time counter: fully unrolled, the 64 row
-                // bits become constants hoisted out of the item loop)
                 const uint4 *src = (const uint4 *)(xc + row0);
                 const uint4 d0 = src[0], d1 = src[1], d2 = src[2], d3 = src[3];
-#pragma unroll 1
-                for (uint32_t k = 0; k < 4; ++k) {
-                    const uint4 dk = k == 0 ? d0 : k == 1 ? d1 : k == 2 ? d2 : d3;
-                    const uint32_t w[4] = {dk.x, dk.y, dk.z, dk.w};
+                // rows past m set no bit: the bit of row r is masked with the
+                // word's valid rows, so every row is one 32-bit LDS OR into
+                // its half of the code's mask word, without a branch
+                const uint32_t cnt = (m - row0) < 64u ? (m - row0) : 64u;
+                const uint32_t ok_lo = cnt >= 32u ? ~0u : ((1u << cnt) - 1u);
+                const uint32_t ok_hi = cnt >= 64u ? ~0u : cnt <= 32u ? 0u : ((1u << (cnt - 32u)) - 1u);
+                char *col = (char *)(pm + q * 64 + lane);
+                const uint32_t w[16] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w,
+                                        d2.x, d2.y, d2.z, d2.w, d3.x, d3.y, d3.z, d3.w};
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-#pragma unroll
-                        for (int by = 0; by < 4; ++by) {
-                            const uint32_t r = 16 * k + 4 * e + by;
-                            if (r < cnt) {
-                                const uint32_t c = (w[e] >> (8 * by)) & 0xffu;
-                                atomicOr((unsigned long long *)(col + c * RS), 1ull << r);
-                            }
-                        }
+                for (int r = 0; r < 64; ++r) {
+                    const uint32_t c = (w[r >> 2] >> (8 * (r & 3))) & 0xffu;
+                    uint32_t *dst = (uint32_t *)(col + c * (RS * 8u)) + (r >> 5);
+                    atomicOr(dst, (r < 32 ? ok_lo : ok_hi) & (1u << (r & 31)));
                 }
             }
         }
@@ -450,16 +446,16 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
                 // is the bit of step (group start + s + 1) of the chunk
                 uint32_t ow_lo = 0, ow_hi = 0;
                 load16(ys, t + 32, Y2);
-                run16<WPL, TB, true, RAW, OWASM>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
+                run16<WPL, TB, true, RAW>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
                                           (uint32_t)(inbits >> 1), ow_lo);
                 load16(ys, t + 48, Y3);
-                run16<WPL, TB, true, RAW, OWASM>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
+                run16<WPL, TB, true, RAW>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
                                           (uint32_t)(inbits >> 17), ow_lo);
                 load16(ys, t + 64, Y0);
-                run16<WPL, TB, true, RAW, OWASM>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
+                run16<WPL, TB, true, RAW>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
                                           (uint32_t)(inbits >> 33), ow_hi);
                 load16(ys, t + 80, Y1);
-                run16<WPL, TB, true, RAW, OWASM>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
+                run16<WPL, TB, true, RAW>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
                                           (uint32_t)(inbits >> 49), ow_hi);
                 // lane 63's carries of the chunk, step e in bit e
                 const uint64_t outbits =
@@ -477,13 +473,13 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
             } else {
                 uint32_t dummy_ow = 0;
                 load16(ys, t + 32, Y2);
-                run16<WPL, TB, false, RAW, OWASM>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
+                run16<WPL, TB, false, RAW>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
                 load16(ys, t + 48, Y3);
-                run16<WPL, TB, false, RAW, OWASM>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
+                run16<WPL, TB, false, RAW>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
                 load16(ys, t + 64, Y0);
-                run16<WPL, TB, false, RAW, OWASM>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
+                run16<WPL, TB, false, RAW>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
                 load16(ys, t + 80, Y1);
-                run16<WPL, TB, false, RAW, OWASM>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
+                run16<WPL, TB, false, RAW>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
             }
         }
         if (a.trace && lane == 0) {
@@ -533,7 +529,8 @@ static const void *fill_entry() {
     else return (const void *)&k_fill<WPL, MODE, RAW>;
 }
 
-const void *fill_symbol(int wpl, int mode, bool raw) {
+const void *fill_symbol(int wpl, int mode, bool raw, int sigma) {
+    (void)sigma;
 #define LCS_FILL_SYM(W, R)                                                              \
     if (wpl == W && raw == R) {                                                         \
         if (mode == kFillTraceback) return fill_entry<W, kFillTraceback, R>();          \
@@ -556,7 +553,7 @@ hipError_t launch_fill(int wpl, int mode, const FillArgs &a, uint32_t grid, hipS
     if (!wpl_fits(a.sigma, wpl)) return hipErrorInvalidValue;
     if (mode == kFillThreshold && (!a.pair_n || !a.thr_t || !a.thr_dec || !a.xsum))
         return hipErrorInvalidValue;
-    const void *fn = fill_symbol(wpl, mode, raw_stream(a.sigma, wpl));
+    const void *fn = fill_symbol(wpl, mode, raw_stream(a.sigma, wpl), a.sigma);
     if (!fn) return hipErrorInvalidValue;
     FillArgs arg = a;
     void *args[] = {&arg};

@@ -169,7 +169,7 @@ constexpr int kTbBlock = 256;
 size_t fill_lds_bytes(int wpl, int sigma, int mode);
 size_t tb_lds_bytes(int wpl, int sigma, int ckpt_every, int nb, int bands);
 
-const void *fill_symbol(int wpl, int mode, bool raw);
+const void *fill_symbol(int wpl, int mode, bool raw, int sigma);
 int fill_block(int wpl, int sigma);   // threads per fill work-group
 const void *tb_symbol(int wpl, int ckpt_every);
 

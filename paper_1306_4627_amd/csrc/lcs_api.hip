@@ -876,10 +876,10 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
             D.fill_waves = fw;
             // with traceback rounds the pass's fill stores no history
             const int mode = bp->rounds ? (int)kFillLength : fill_mode(flags);
-            D.fill_grid = resident_grid(ctx, fill_symbol(C.wpl, mode, raw_stream(sigma, C.wpl)),
+            D.fill_grid = resident_grid(ctx, fill_symbol(C.wpl, mode, raw_stream(sigma, C.wpl), sigma),
                                         fill_lds_bytes(C.wpl, sigma, mode), (D.nitems + fw - 1) / fw,
                                         cap > 0 ? (cap + fw - 1) / fw : 0, 64 * fw);
-            const void *tfn = fill_symbol(C.wpl, kFillTraceback, raw_stream(sigma, C.wpl));
+            const void *tfn = fill_symbol(C.wpl, kFillTraceback, raw_stream(sigma, C.wpl), sigma);
             const size_t tlds = fill_lds_bytes(C.wpl, sigma, kFillTraceback);
             for (uint32_t r = 0; r < C.n_rounds; ++r) {
                 const uint32_t ni = C.rd_item_off[r + 1] - C.rd_item_off[r];

@@ -343,6 +343,30 @@ def test_error_paths_leave_outputs_untouched(ctx, lcs):
     small.close()
 
 
+@pytest.mark.parametrize("sigma", [20, 40])
+def test_lengths_with_next_item_prefetch(ctx, lcs, sigma):
+    # alphabets whose match masks leave two waves or fewer per SIMD at two
+    # words per lane: the lengths-only fill prefetches each wave's next item
+    # (its ticket, lane tables, X codes and first stream values) during the
+    # current one; short pairs packed many per item, single-item pairs and
+    # chains of several items, ragged lengths, empty pairs
+    g = inputs.rng(8600 + sigma)
+    al = bytes(range(65, 65 + sigma))
+    pairs = []
+    for k in range(300):
+        m = int(g.integers(0, 1100)) if k % 10 else int(g.integers(8000, 30000))
+        n = int(g.integers(0, 1100)) if k % 7 else int(g.integers(2000, 9000))
+        pairs.append((_rand(g, m, al), _rand(g, n, al)))
+    want = _oracle_lengths(pairs)
+    for wpl in (2, 1):
+        _say(f"prefetch fill sigma={sigma} wpl={wpl}")
+        with lcs.Batch(ctx, pairs, al, graph=True, words_per_lane=wpl) as b:
+            for rep in range(2):
+                b.run()
+                assert np.array_equal(b.lengths(), want), (wpl, rep)
+        assert np.array_equal(lcs.lcs_length_batch(ctx, pairs, al), want)
+
+
 # --------------------------------------------------------------------------
 # full-size workloads, in the launch configuration of the benchmark
 # --------------------------------------------------------------------------
