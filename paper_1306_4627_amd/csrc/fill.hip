@@ -117,6 +117,34 @@ __device__ __forceinline__ void run16(const uint32_t (&Yg)[8], uint32_t t, const
     }
 }
 
+// One chunk: 64 column steps t..t+63, four groups of sixteen stream values
+// in a ring (Y0, Y1 hold the chunk's first two groups on entry; the group 32
+// steps ahead is requested before each group runs, so on return Y0, Y1 hold
+// the next chunk's first two).  `inbits`: with CHAIN, the hand-over bits of
+// the chunk (bit s = step s); ow_lo, ow_hi receive lane 63's carries of the
+// chunk's two halves.  (Reading each eight steps' match masks while the
+// eight before them run, with two sets of mask registers, measured no faster
+// on short protein pairs and 2-6% slower on the related DNA batch, whose
+// lengths-only fill it took from four waves per SIMD to three.)
+template <int WPL, bool TB, bool CHAIN, bool RAW>
+__device__ __forceinline__ void run64(uint32_t (&Y0)[8], uint32_t (&Y1)[8], uint32_t (&Y2)[8],
+                                      uint32_t (&Y3)[8], const uint16_t *ys, uint32_t t,
+                                      const char *lanecol, uint64_t notstart, uint64_t &cmask,
+                                      uint32_t &acc, uint32_t *cbp, uint32_t (&vlo)[WPL],
+                                      uint32_t (&vhi)[WPL], uint64_t inbits, uint32_t &ow_lo,
+                                      uint32_t &ow_hi) {
+    const uint32_t in0 = (uint32_t)(inbits >> 1), in1 = (uint32_t)(inbits >> 17);
+    const uint32_t in2 = (uint32_t)(inbits >> 33), in3 = (uint32_t)(inbits >> 49);
+    load16(ys, t + 32, Y2);
+    run16<WPL, TB, CHAIN, RAW>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, in0, ow_lo);
+    load16(ys, t + 48, Y3);
+    run16<WPL, TB, CHAIN, RAW>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, in1, ow_lo);
+    load16(ys, t + 64, Y0);
+    run16<WPL, TB, CHAIN, RAW>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, in2, ow_hi);
+    load16(ys, t + 80, Y1);
+    run16<WPL, TB, CHAIN, RAW>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, in3, ow_hi);
+}
+
 // Zero bits among this lane's valid rows of V: the lane's share of
 // c[m][j] for the column it holds (rows above m are padding).
 template <int WPL>
@@ -445,18 +473,8 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
                 // hand-over bits of the next step: bit s of each group's word
                 // is the bit of step (group start + s + 1) of the chunk
                 uint32_t ow_lo = 0, ow_hi = 0;
-                load16(ys, t + 32, Y2);
-                run16<WPL, TB, true, RAW>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
-                                          (uint32_t)(inbits >> 1), ow_lo);
-                load16(ys, t + 48, Y3);
-                run16<WPL, TB, true, RAW>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
-                                          (uint32_t)(inbits >> 17), ow_lo);
-                load16(ys, t + 64, Y0);
-                run16<WPL, TB, true, RAW>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
-                                          (uint32_t)(inbits >> 33), ow_hi);
-                load16(ys, t + 80, Y1);
-                run16<WPL, TB, true, RAW>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi,
-                                          (uint32_t)(inbits >> 49), ow_hi);
+                run64<WPL, TB, true, RAW>(Y0, Y1, Y2, Y3, ys, t, lanecol, notstart, cmask, acc,
+                                                cbp, vlo, vhi, inbits, ow_lo, ow_hi);
                 // lane 63's carries of the chunk, step e in bit e
                 const uint64_t outbits =
                     ((uint64_t)__builtin_bitreverse32(ow_hi) << 32) | __builtin_bitreverse32(ow_lo);
@@ -471,15 +489,9 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
             } else {
-                uint32_t dummy_ow = 0;
-                load16(ys, t + 32, Y2);
-                run16<WPL, TB, false, RAW>(Y0, t, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
-                load16(ys, t + 48, Y3);
-                run16<WPL, TB, false, RAW>(Y1, t + 16, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
-                load16(ys, t + 64, Y0);
-                run16<WPL, TB, false, RAW>(Y2, t + 32, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
-                load16(ys, t + 80, Y1);
-                run16<WPL, TB, false, RAW>(Y3, t + 48, lanecol, notstart, cmask, acc, cbp, vlo, vhi, 0u, dummy_ow);
+                uint32_t dummy_lo = 0, dummy_hi = 0;
+                run64<WPL, TB, false, RAW>(Y0, Y1, Y2, Y3, ys, t, lanecol, notstart, cmask, acc,
+                                                 cbp, vlo, vhi, 0ull, dummy_lo, dummy_hi);
             }
         }
         if (a.trace && lane == 0) {

@@ -6,6 +6,17 @@
 
 namespace lcs {
 
+// One region of the Y stream, as the stream builder reads it (32 bytes,
+// one pair of 16-byte loads).
+struct SegInfo {
+    uint64_t begin;   // first element of the region
+    uint64_t yoff;    // offset of its pair's Y in the Y arena
+    uint32_t len;     // region length in elements
+    uint32_t pre;     // sentinel elements before column 0
+    uint32_t n;       // columns of its pair (0 for an all-sentinel region)
+    uint32_t shift;   // log2 of the stream scale (words_per_lane * 512), or 0
+};
+
 // Symbol remap and Y-stream construction (all device pointers).
 struct PrepArgs {
     const uint8_t *lut;        // 256 entries: byte -> code (validated on the host)
@@ -13,12 +24,7 @@ struct PrepArgs {
     uint8_t *xcodes;           // X arena (codes), same offsets
     uint64_t xarena;           // bytes in the X arena
     const uint8_t *ybytes;     // Y arena (raw bytes)
-    const uint64_t *seg_yoff;  // per stream region: offset of its Y in the Y arena
-    const uint32_t *seg_n;     // columns of its pair (0 for an all-sentinel region)
-    const uint64_t *seg_begin; // first element of the region
-    const uint32_t *seg_pre;   // sentinel elements before column 0
-    const uint64_t *seg_len;   // region length in elements
-    const uint8_t *seg_shift;  // log2 of the stream scale (words_per_lane * 512)
+    const SegInfo *seg;        // stream regions
     uint32_t nseg;
     const uint32_t *blk_seg;   // region of each 64-element block of the stream
     uint64_t nblk;             // 64-element blocks in the stream (regions are

@@ -144,10 +144,8 @@ struct lcs_batch {
     uint32_t *em_pair = nullptr, *em_w0 = nullptr;
     std::vector<uint64_t> diag_off_host;
     uint32_t *pair_m = nullptr, *pair_n = nullptr;
-    uint64_t *seg_yoff = nullptr, *seg_begin = nullptr, *seg_len = nullptr;
+    SegInfo *seg = nullptr;        // Y-stream regions
     uint32_t *blk_seg = nullptr;   // region of each 64-element block of the Y stream
-    uint32_t *seg_n = nullptr, *seg_pre = nullptr;
-    uint8_t *seg_shift = nullptr;
     uint16_t *ystream = nullptr;
     uint8_t *out = nullptr;
     uint32_t *zero = nullptr;
@@ -479,12 +477,7 @@ static size_t carve(lcs_batch *b, char *base) {
     const bool thr = (b->flags & LCS_THRESHOLD) != 0;
     b->thr_t = thr ? cv.take<uint32_t>(np + 1) : nullptr;
     const size_t ns = p.segs.size();
-    b->seg_yoff = cv.take<uint64_t>(ns + 1);
-    b->seg_begin = cv.take<uint64_t>(ns + 1);
-    b->seg_len = cv.take<uint64_t>(ns + 1);
-    b->seg_n = cv.take<uint32_t>(ns + 1);
-    b->seg_pre = cv.take<uint32_t>(ns + 1);
-    b->seg_shift = cv.take<uint8_t>(ns + 1);
+    b->seg = cv.take<SegInfo>(ns + 1);
     b->blk_seg = cv.take<uint32_t>(p.ys_elems / 64 + 1);
     b->cls.resize(p.classes.size());
     for (size_t ci = 0; ci < p.classes.size(); ++ci) {
@@ -779,18 +772,20 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     }
     const Plan &p = bp->plan;
     const size_t ns = p.segs.size();
-    std::vector<uint64_t> s_yoff(ns + 1, 0), s_begin(ns + 1, 0), s_len(ns + 1, 0);
-    std::vector<uint32_t> s_n(ns + 1, 0), s_pre(ns + 1, 0);
-    std::vector<uint8_t> s_shift(ns + 1, 0);
+    std::vector<SegInfo> seginfo(ns + 1);
     for (size_t s = 0; s < ns; ++s) {
         const Segment &sg = p.segs[s];
-        s_begin[s] = sg.begin;
-        s_len[s] = sg.len;
-        s_pre[s] = sg.pre;
-        s_shift[s] = sg.shift;
+        if (sg.len > 0xffffffffull) return fail(LCS_ERR_TOO_LONG);
+        SegInfo &si = seginfo[s];
+        si.begin = sg.begin;
+        si.len = (uint32_t)sg.len;
+        si.pre = sg.pre;
+        si.shift = sg.shift;
+        si.n = 0;
+        si.yoff = 0;
         if (sg.pair != kNoPair) {
-            s_n[s] = (uint32_t)pairs[sg.pair].n;
-            s_yoff[s] = yoff[sg.pair];
+            si.n = (uint32_t)pairs[sg.pair].n;
+            si.yoff = yoff[sg.pair];
         }
     }
     hipStream_t st0 = bp->hooks.stream ? bp->hooks.stream : ctx->own_stream;
@@ -815,12 +810,7 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     UP(bp->em_w0, bp->em_w0_host.data(), bp->em_w0_host.size() * 4);
     UP(bp->pair_m, hm.data(), count * 4);
     UP(bp->pair_n, hn.data(), count * 4);
-    UP(bp->seg_yoff, s_yoff.data(), ns * 8);
-    UP(bp->seg_begin, s_begin.data(), ns * 8);
-    UP(bp->seg_len, s_len.data(), ns * 8);
-    UP(bp->seg_n, s_n.data(), ns * 4);
-    UP(bp->seg_pre, s_pre.data(), ns * 4);
-    UP(bp->seg_shift, s_shift.data(), ns);
+    UP(bp->seg, seginfo.data(), ns * sizeof(SegInfo));
     {
         // regions are whole 64-element blocks, back to back
         std::vector<uint32_t> bs(p.ys_elems / 64, 0);
@@ -980,12 +970,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
     pa.xcodes = b->xcodes;
     pa.xarena = b->xarena;
     pa.ybytes = b->ybytes;
-    pa.seg_yoff = b->seg_yoff;
-    pa.seg_n = b->seg_n;
-    pa.seg_begin = b->seg_begin;
-    pa.seg_pre = b->seg_pre;
-    pa.seg_len = b->seg_len;
-    pa.seg_shift = b->seg_shift;
+    pa.seg = b->seg;
     pa.nseg = (uint32_t)p.segs.size();
     pa.blk_seg = b->blk_seg;
     pa.nblk = p.ys_elems / 64;

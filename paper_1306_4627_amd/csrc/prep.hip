@@ -6,23 +6,43 @@
 namespace lcs {
 
 // --------------------------------------------------------------------------
-// prep: symbol remap (bytes -> codes), Y streams, zeroing
+// prep: symbol remap (bytes -> codes), Y streams, zeroing -- one launch
 // --------------------------------------------------------------------------
+
+// The work-groups of the one prep launch split into three ranges: the X
+// remap, the zeroing and the Y streams.  All three only depend on the
+// batch's inputs, so they run side by side.
+struct PrepSplit {
+    uint32_t remap_end, zero_end, total;
+};
+
+static PrepSplit prep_split(const PrepArgs &a, uint64_t xbytes_n) {
+    PrepSplit p{};
+    uint64_t rb = (xbytes_n / 16 + 255) / 256;
+    if (rb > 4096) rb = 4096;
+    const uint64_t zw = a.npairs + a.nzero + a.nzero64;
+    uint64_t zb = (zw + 255) / 256;
+    if (zb > 1024) zb = 1024;
+    if (zb < 1) zb = 1;
+    uint64_t sb = (a.nblk * 2 + 255) / 256;
+    if (sb > 16384) sb = 16384;
+    p.remap_end = (uint32_t)rb;
+    p.zero_end = (uint32_t)(rb + zb);
+    p.total = (uint32_t)(rb + zb + sb);
+    return p;
+}
 
 // Symbol remap of the X arena, sixteen bytes per thread (both arenas start
 // 256-byte aligned), the byte -> code table in LDS.
-__global__ __launch_bounds__(256) void k_remap_x(const uint8_t *__restrict__ lut_g,
-                                                 const uint8_t *__restrict__ src,
-                                                 uint8_t *__restrict__ dst, uint64_t n) {
-    __shared__ uint8_t lut[256];
-    lut[threadIdx.x] = lut_g[threadIdx.x];
-    __syncthreads();
+__device__ __forceinline__ void remap_x(const uint8_t *lut, const uint8_t *__restrict__ src,
+                                        uint8_t *__restrict__ dst, uint64_t n, uint32_t block,
+                                        uint32_t blocks) {
     const auto map4 = [&](uint32_t w) {
         return (uint32_t)lut[w & 0xff] | ((uint32_t)lut[(w >> 8) & 0xff] << 8) |
                ((uint32_t)lut[(w >> 16) & 0xff] << 16) | ((uint32_t)lut[w >> 24] << 24);
     };
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 16;
-    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16; i < n; i += stride) {
+    const uint64_t stride = (uint64_t)blocks * blockDim.x * 16;
+    for (uint64_t i = ((uint64_t)block * blockDim.x + threadIdx.x) * 16; i < n; i += stride) {
         if (i + 16 <= n) {
             const uint4 w = *(const uint4 *)(src + i);
             uint4 r;
@@ -37,72 +57,9 @@ __global__ __launch_bounds__(256) void k_remap_x(const uint8_t *__restrict__ lut
     }
 }
 
-// One thread per sixteen stream elements over the whole stream (grid-stride):
-// codes of Y at columns 0..n-1 of each region, the sentinel code everywhere
-// else in it, each shifted into a byte offset of its row of match masks.
-// The region of every 64-element block comes from a table, so a batch of
-// many short regions costs no more work-groups than one of a few long ones.
-__global__ __launch_bounds__(256) void k_streams(PrepArgs a) {
-    // the byte -> code table in LDS; each thread writes two groups of eight
-    // stream values (16 bytes each, aligned: regions start at multiples of 64
-    // elements)
-    __shared__ uint8_t lut[256];
-    lut[threadIdx.x] = a.lut[threadIdx.x];
-    __syncthreads();
-    const uint64_t halves = a.nblk * 4;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t h = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; h < halves; h += stride) {
-        const uint32_t s = a.blk_seg[h >> 2];
-        const uint64_t k0 = h * 16 - a.seg_begin[s];  // element offset in the region
-        const uint64_t len = a.seg_len[s];
-        if (k0 >= len) continue;                      // padding to the block
-        const uint64_t pre = a.seg_pre[s];
-        const uint64_t n = a.seg_n[s];
-        const uint32_t sh = a.seg_shift[s];
-        const uint8_t *y = a.ybytes + a.seg_yoff[s];
-        const uint32_t sent = (uint32_t)a.sentinel << sh;
-        const auto group = [&](uint64_t kg) {
-            uint32_t c[8];
-            if (kg >= pre && kg + 8 <= pre + n) {
-                // eight bytes of Y from two aligned 8-byte reads (the Y arena
-                // is padded by 64 bytes)
-                const uintptr_t ad = (uintptr_t)(y + (kg - pre));
-                const uint64_t *al = (const uint64_t *)(ad & ~(uintptr_t)7);
-                const uint32_t s8 = (uint32_t)(ad & 7) * 8;
-                const uint64_t lo = al[0], hi = al[1];
-                const uint64_t v = s8 ? (lo >> s8) | (hi << (64 - s8)) : lo;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) c[e] = (uint32_t)(v >> (8 * e)) & 0xffu;
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const uint64_t k = kg + e;
-                    c[e] = (k >= pre && k - pre < n) ? (uint32_t)y[k - pre] : 0x100u;
-                }
-            }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) c[e] = c[e] == 0x100u ? sent : ((uint32_t)lut[c[e]] << sh);
-            uint4 v;
-            v.x = c[0] | (c[1] << 16);
-            v.y = c[2] | (c[3] << 16);
-            v.z = c[4] | (c[5] << 16);
-            v.w = c[6] | (c[7] << 16);
-            return v;
-        };
-        const uint4 v0 = group(k0);
-        if (k0 + 8 < len) {
-            const uint4 v1 = group(k0 + 8);
-            *(uint4 *)(a.ystream + h * 16) = v0;
-            *(uint4 *)(a.ystream + h * 16 + 8) = v1;
-        } else {
-            *(uint4 *)(a.ystream + h * 16) = v0;
-        }
-    }
-}
-
-__global__ void k_zero(PrepArgs a) {
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+__device__ __forceinline__ void zero_words(const PrepArgs &a, uint32_t block, uint32_t blocks) {
+    const uint64_t tid = (uint64_t)block * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)blocks * blockDim.x;
     for (uint64_t k = tid; k < a.npairs; k += stride) a.out_len[k] = 0;
     for (uint64_t k = tid; k < a.nzero; k += stride) a.zero_words[k] = 0;
     for (uint64_t k = tid; k < a.nzero64; k += stride) a.zero64[k] = 0;
@@ -115,19 +72,82 @@ __global__ void k_zero(PrepArgs a) {
         }
 }
 
+// Eight stream values of a region from element kg on: codes of Y at columns
+// 0..n-1, the sentinel code everywhere else, each shifted into a byte offset
+// of its row of match masks; two per 32-bit word.
+__device__ __forceinline__ uint4 stream8(const uint8_t *lut, const uint8_t *y, uint64_t kg,
+                                         uint32_t pre, uint32_t n, uint32_t sh, uint32_t sent) {
+    uint32_t c[8];
+    if (kg >= pre && kg + 8 <= (uint64_t)pre + n) {
+        // eight bytes of Y from two aligned 8-byte reads (the Y arena is
+        // padded by 64 bytes)
+        const uintptr_t ad = (uintptr_t)(y + (kg - pre));
+        const uint64_t *al = (const uint64_t *)(ad & ~(uintptr_t)7);
+        const uint32_t s8 = (uint32_t)(ad & 7) * 8;
+        const uint64_t lo = al[0], hi = al[1];
+        const uint64_t v = s8 ? (lo >> s8) | (hi << (64 - s8)) : lo;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) c[e] = (uint32_t)lut[(uint32_t)(v >> (8 * e)) & 0xffu] << sh;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint64_t k = kg + e;
+            c[e] = (k >= pre && k - pre < n) ? ((uint32_t)lut[y[k - pre]] << sh) : sent;
+        }
+    }
+    uint4 v;
+    v.x = c[0] | (c[1] << 16);
+    v.y = c[2] | (c[3] << 16);
+    v.z = c[4] | (c[5] << 16);
+    v.w = c[6] | (c[7] << 16);
+    return v;
+}
+
+// One thread per 32 stream elements (grid-stride over the stream's 64-element
+// blocks, two threads a block): the region of every block comes from a
+// table, its description from one 32-byte record, so a batch of many short
+// regions costs no more threads than one of a few long ones.
+__device__ __forceinline__ void streams(const PrepArgs &a, const uint8_t *lut, uint32_t block,
+                                        uint32_t blocks) {
+    const uint64_t halves = a.nblk * 2;
+    const uint64_t stride = (uint64_t)blocks * blockDim.x;
+    for (uint64_t h = (uint64_t)block * blockDim.x + threadIdx.x; h < halves; h += stride) {
+        const SegInfo &sg = a.seg[a.blk_seg[h >> 1]];
+        const uint4 m0 = *(const uint4 *)&sg;              // begin, yoff
+        const uint4 m1 = *((const uint4 *)&sg + 1);        // len, pre, n, shift
+        const uint64_t begin = ((uint64_t)m0.y << 32) | m0.x;
+        const uint64_t yoff = ((uint64_t)m0.w << 32) | m0.z;
+        const uint64_t k0 = h * 32 - begin;   // element offset in the region
+        if (k0 >= m1.x) continue;             // padding to the block
+        const uint8_t *y = a.ybytes + yoff;
+        const uint32_t sent = (uint32_t)a.sentinel << m1.w;
+        uint4 v[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) v[g] = stream8(lut, y, k0 + 8 * g, m1.y, m1.z, m1.w, sent);
+        uint4 *dst = (uint4 *)(a.ystream + h * 32);
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            if (k0 + 8 * g < m1.x) dst[g] = v[g];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_prep(PrepArgs a, uint64_t xbytes_n, PrepSplit sp) {
+    __shared__ uint8_t lut[256];
+    lut[threadIdx.x] = a.lut[threadIdx.x];
+    __syncthreads();
+    const uint32_t b = blockIdx.x;
+    if (b < sp.remap_end) {
+        remap_x(lut, a.xbytes, a.xcodes, xbytes_n, b, sp.remap_end);
+    } else if (b < sp.zero_end) {
+        zero_words(a, b - sp.remap_end, sp.zero_end - sp.remap_end);
+    } else {
+        streams(a, lut, b - sp.zero_end, sp.total - sp.zero_end);
+    }
+}
+
 hipError_t launch_prep(const PrepArgs &a, uint64_t xbytes_n, hipStream_t s) {
-    if (xbytes_n) {
-        uint64_t blocks = (xbytes_n / 16 + 255) / 256;
-        if (blocks > 8192) blocks = 8192;
-        hipLaunchKernelGGL(k_remap_x, dim3((uint32_t)blocks), dim3(256), 0, s, a.lut, a.xbytes,
-                           a.xcodes, xbytes_n);
-    }
-    hipLaunchKernelGGL(k_zero, dim3(512), dim3(256), 0, s, a);
-    if (a.nblk) {
-        uint64_t blocks = (a.nblk * 4 + 255) / 256;
-        if (blocks > 32768) blocks = 32768;
-        hipLaunchKernelGGL(k_streams, dim3((uint32_t)blocks), dim3(256), 0, s, a);
-    }
+    const PrepSplit sp = prep_split(a, xbytes_n);
+    hipLaunchKernelGGL(k_prep, dim3(sp.total), dim3(256), 0, s, a, xbytes_n, sp);
     return hipGetLastError();
 }
 
