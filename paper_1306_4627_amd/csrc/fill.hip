@@ -201,6 +201,41 @@ __device__ __forceinline__ uint32_t clamp_col(int64_t j, uint32_t n) {
 // the items of a chain once its pair is.
 constexpr uint32_t kThrEvery = 4;   // chunks between threshold checks of an item
 
+// Queue place of a wave's next item (lane 0 only).  The queue holds the items
+// longest first; left alone, the waves starting together take the first
+// places in no particular order, and a SIMD may get several of the longest
+// items at once: its waves then share its issue until the end of the pass
+// while other SIMDs run out of work.  With bands, a wave's first item is the
+// next place of band r, r its rank among this launch's waves on its SIMD, so
+// each SIMD starts with one item of each band.  Later items (and a first item
+// whose band is used up) come from places the bands left untaken, bands in
+// order, then from the places after the bands.  Every place is taken once;
+// places of one band go out in order, and a band's leftovers before any later
+// place, so an item's feeder (the place before it) has been taken first or is
+// among the few leftovers the next free wave takes.
+__device__ __forceinline__ uint32_t next_place(const FillArgs &a, bool first) {
+    const uint32_t B = a.band_size;
+    if (!B) return atomicAdd(a.queue, 1u);
+    if (first) {
+        const uint32_t hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);    // HW_ID
+        const uint32_t xcc = __builtin_amdgcn_s_getreg((31 << 11) | 20);  // XCC_ID
+        const uint32_t key = ((xcc & 15u) << 10) | (((hw >> 13) & 7u) << 7) |
+                             (((hw >> 12) & 1u) << 6) | (((hw >> 8) & 15u) << 2) | ((hw >> 4) & 3u);
+        const uint32_t r = atomicAdd(a.simd_rank + key, 1u);
+        if (r < a.nbands) {
+            const uint32_t q = atomicAdd(a.band_next + r, 1u);
+            if (q < B) return r * B + q;
+        }
+    }
+    for (uint32_t k = 0; k < a.nbands; ++k) {
+        if (__hip_atomic_load(a.band_next + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < B) {
+            const uint32_t q = atomicAdd(a.band_next + k, 1u);
+            if (q < B) return k * B + q;
+        }
+    }
+    return a.nbands * B + atomicAdd(a.queue, 1u);
+}
+
 template <int WPL, int MODE, bool RAW>
 __device__ __forceinline__ void fill_body(const FillArgs &a) {
     constexpr bool TB = MODE == kFillTraceback;
@@ -224,9 +259,11 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
         a.clk[1] = __builtin_amdgcn_s_memrealtime();
     }
 
+    bool first = true;
     for (;;) {
         uint32_t ticket = 0;
-        if (lane == 0) ticket = atomicAdd(a.queue, 1u);
+        if (lane == 0) ticket = next_place(a, first);
+        first = false;
         ticket = __builtin_amdgcn_readfirstlane(ticket);
         if (ticket >= a.item_end - a.item_begin) {
             if (clk_lane) {

@@ -68,6 +68,16 @@ struct FillArgs {
     uint32_t *cbits;
     uint64_t *xfer;            // hand-over words, two per chunk per feeder (zeroed)
     uint32_t *queue;           // work counter (zeroed before the launch)
+    // First-item bands (optional, band_size 0 = off): the first nbands *
+    // band_size queue places form nbands bands; a wave's first item is the
+    // next place of the band of its rank among the launch's waves on its
+    // SIMD (simd_rank: kSimdKeys counters, band_next: kMaxBands counters,
+    // all zeroed before the launch), so that every SIMD starts with one item
+    // of each band instead of several of the longest ones
+    uint32_t *simd_rank;
+    uint32_t *band_next;
+    uint32_t band_size;
+    uint32_t nbands;
     uint32_t *error;           // set to 1 when a bounded wait runs out
     uint32_t item_begin;
     uint32_t item_end;
@@ -96,6 +106,11 @@ struct FillArgs {
 };
 
 constexpr int kTraceWords = 6;
+
+// First-item bands: SIMD keys from HW_ID and XCC_ID (XCC 4 bits, shader
+// engine 3, shader array 1, CU 4, SIMD 2) and the most bands of a launch.
+constexpr uint32_t kSimdKeys = 1u << 14;
+constexpr uint32_t kMaxBands = 8;
 
 // What a fill launch computes: lengths only, lengths plus the checkpoints the
 // traceback reads, or the threshold pass (lengths of the pairs it does not

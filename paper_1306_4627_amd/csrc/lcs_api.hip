@@ -75,6 +75,11 @@ struct ClassDev {
     uint64_t *trace = nullptr;         // schedule records of the fill items (LCS_FILL_TRACE)
     uint32_t *plain_ctr = nullptr;     // plain mode: kQueues queue counters per pair
     uint32_t *q_fill = nullptr, *q_spec = nullptr, *q_fix = nullptr, *q_seal = nullptr;
+    // the pass's fill launch: per-SIMD rank counters and band counters of
+    // its first-item bands (zeroed with the queue counters), band size and
+    // count (0 = no bands)
+    uint32_t *simd_rank = nullptr, *band_next = nullptr;
+    uint32_t fill_band_size = 0, fill_nbands = 0;
     uint32_t fill_grid = 1, sp_grid = 1, fx_grid = 1, sl_grid = 1;
     int fill_waves = 4;                // waves per fill work-group
     int nb = 1;                        // traceback tiles per band recomputed together
@@ -537,6 +542,7 @@ static size_t carve(lcs_batch *b, char *base) {
         const ClassPlan &C = p.classes[ci];
         nz += kQueues;
         if (b->plain) nz += kQueues * C.tb_pair.size();
+        else nz += kSimdKeys + kMaxBands;
         nz += kQueues * C.n_rounds;
     }
     b->zero = cv.take<uint32_t>(nz);
@@ -598,7 +604,13 @@ static size_t carve(lcs_batch *b, char *base) {
         D.q_seal = b->zero ? b->zero + zc + 3 : nullptr;
         zc += kQueues;
         D.plain_ctr = b->zero ? b->zero + zc : nullptr;
-        if (b->plain) zc += kQueues * D.ntb;
+        if (b->plain) {
+            zc += kQueues * D.ntb;
+        } else {
+            D.simd_rank = b->zero ? b->zero + zc : nullptr;
+            D.band_next = b->zero ? b->zero + zc + kSimdKeys : nullptr;
+            zc += kSimdKeys + kMaxBands;
+        }
         D.q_round = b->zero ? b->zero + zc : nullptr;
         zc += kQueues * C.n_rounds;
     }
@@ -869,6 +881,16 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
             D.fill_grid = resident_grid(ctx, fill_symbol(C.wpl, mode, raw_stream(sigma, C.wpl), sigma),
                                         fill_lds_bytes(C.wpl, sigma, mode), (D.nitems + fw - 1) / fw,
                                         cap > 0 ? (cap + fw - 1) / fw : 0, 64 * fw);
+            // first-item bands: one band per wave every SIMD holds (four
+            // SIMDs per CU), each as many places as there are SIMDs
+            {
+                const uint64_t simds = (uint64_t)ctx->num_cus * 4;
+                uint64_t nbd = simds ? (uint64_t)D.fill_grid * (uint64_t)fw / simds : 0;
+                nbd = std::min<uint64_t>(nbd, kMaxBands);
+                if (simds) nbd = std::min<uint64_t>(nbd, D.nitems / simds);
+                D.fill_nbands = bp->plain ? 0 : (uint32_t)nbd;
+                D.fill_band_size = D.fill_nbands ? (uint32_t)simds : 0;
+            }
             const void *tfn = fill_symbol(C.wpl, kFillTraceback, raw_stream(sigma, C.wpl), sigma);
             const size_t tlds = fill_lds_bytes(C.wpl, sigma, kFillTraceback);
             for (uint32_t r = 0; r < C.n_rounds; ++r) {
@@ -1016,6 +1038,10 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         fa.cbits = D.cbits;
         fa.xfer = D.xfer;
         fa.queue = D.q_fill;
+        fa.simd_rank = D.simd_rank;
+        fa.band_next = D.band_next;
+        fa.band_size = D.fill_band_size;
+        fa.nbands = D.fill_nbands;
         fa.error = b->error;
         fa.item_begin = 0;
         fa.item_end = D.nitems;
@@ -1131,6 +1157,8 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
                     fa.it_cb = D.it_rcb;
                     fa.out_len = nullptr;
                     fa.queue = q;
+                    fa.band_size = 0;
+                    fa.nbands = 0;
                     fa.clk = nullptr;
                     fa.trace = nullptr;
                     HIP_TRY(launch_fill(D.wpl, kFillTraceback, fa, D.rd_fill_grid[r], s));
@@ -1170,6 +1198,8 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
                 fa.item_begin = D.pl_begin[k];
                 fa.item_end = D.pl_end[k];
                 fa.queue = ctr + kQueues * k;
+                fa.band_size = 0;
+                fa.nbands = 0;
                 uint32_t g = (fa.item_end - fa.item_begin + D.fill_waves - 1) / D.fill_waves;
                 HIP_TRY(launch_fill(D.wpl, mode, fa, g, s));
                 if (tb) {
