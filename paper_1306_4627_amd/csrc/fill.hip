@@ -494,15 +494,30 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
             // a device-scope load takes about as long as a chunk of a wave
             // that has its SIMD to itself, so a later request would stall the
             // next chunk's start.  Words not yet written are polled again.
-            if (live_in) {
-                pw0 = __hip_atomic_load(xf_in + 2 * c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                pw1 = __hip_atomic_load(xf_in + 2 * c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (THR && (c + 1 + kThrEvery - phase) % kThrEvery == 0)
-                    pw2 = __hip_atomic_load(xs_in + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // With the traceback history, these two reads and the checkpoint
+            // store below are issued on every path -- an item with no feeder
+            // reads, and a chunk with no checkpoint writes, the junk words --
+            // so that the compiler counts them in its memory-counter waits for
+            // the stream reads issued before them; under a branch they made it
+            // wait for everything outstanding, the hand-over reads just
+            // requested included (the 262144-row pair's traceback fill: 5%
+            // slower).  The lengths-only fill keeps the branch: issued on
+            // every path, the reads moved its full wait to the chunk start,
+            // where it catches the stream read issued 16 steps earlier (3%
+            // slower on a SIMD of its own, the same with four waves).
+            if (TB || live_in) {
+                const uint64_t *src = live_in ? xf_in + 2 * c : a.junk;
+                pw0 = __hip_atomic_load(const_cast<uint64_t *>(src), __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+                pw1 = __hip_atomic_load(const_cast<uint64_t *>(src) + 1, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
             }
+            if (THR && live_in && (c + 1 + kThrEvery - phase) % kThrEvery == 0)
+                pw2 = __hip_atomic_load(xs_in + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (THR) pdec_nx = load_state(a.thr_dec, pair);
-            if (TB && ((c * 64u) % (uint32_t)a.ckpt_every) == 0) {
-                uint64_t *dst = ckp + (size_t)((c * 64u) / (uint32_t)a.ckpt_every) * RS;
+            if (TB) {
+                const bool ck = ((c * 64u) % (uint32_t)a.ckpt_every) == 0;
+                uint64_t *dst = ck ? ckp + (size_t)((c * 64u) / (uint32_t)a.ckpt_every) * RS : a.junk + lane;
 #pragma unroll
                 for (int q = 0; q < WPL; ++q) dst[q * 64] = ((uint64_t)vhi[q] << 32) | vlo[q];
             }

@@ -79,6 +79,9 @@ struct FillArgs {
     uint32_t band_size;
     uint32_t nbands;
     uint32_t *error;           // set to 1 when a bounded wait runs out
+    // kJunkWords words of any content: the chunk-start reads of an item with
+    // no feeder and the checkpoint stores of chunks that keep none go here
+    uint64_t *junk;
     uint32_t item_begin;
     uint32_t item_end;
     // optional: the items to run are item_list[item_begin .. item_end)
@@ -106,6 +109,7 @@ struct FillArgs {
 };
 
 constexpr int kTraceWords = 6;
+constexpr uint32_t kJunkWords = 8 * 64;   // eight words per lane
 
 // First-item bands: SIMD keys from HW_ID and XCC_ID (XCC 4 bits, shader
 // engine 3, shader array 1, CU 4, SIMD 2) and the most bands of a launch.

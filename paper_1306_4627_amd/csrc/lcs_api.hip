@@ -159,6 +159,7 @@ struct lcs_batch {
     uint64_t nzero64 = 0;
     uint32_t *error = nullptr;
     uint64_t *clk = nullptr;       // clock counters of the last fill launch
+    uint64_t *junk = nullptr;      // fill: target of reads and stores a chunk does not need
     // threshold pass: per-pair target length (host copy and device) and
     // answer word (0 open, 1 reaches the target, 2 cannot; read back with the
     // lengths)
@@ -552,6 +553,7 @@ static size_t carve(lcs_batch *b, char *base) {
     b->readback_bytes = (size_t)((char *)(b->out + b->out_bytes) - (char *)b->out_len);
     // ---- device only ----
     b->clk = cv.take<uint64_t>(4);
+    b->junk = cv.take<uint64_t>(kJunkWords);
     b->xcodes = cv.take<uint8_t>(b->xarena + 64);
     b->ystream = cv.take<uint16_t>(p.ys_elems + 64);
     // zeroed before every pass, 64-bit: traceback bitmaps, then the carry
@@ -1043,6 +1045,7 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         fa.band_size = D.fill_band_size;
         fa.nbands = D.fill_nbands;
         fa.error = b->error;
+        fa.junk = b->junk;
         fa.item_begin = 0;
         fa.item_end = D.nitems;
         fa.prio_half = D.prio_half;
