@@ -192,7 +192,8 @@ constexpr int kFillBlock = 256;   // at most four independent waves per work-gro
 constexpr int kTbBlock = 256;
 
 size_t fill_lds_bytes(int wpl, int sigma, int mode);
-size_t tb_lds_bytes(int wpl, int sigma, int ckpt_every, int nb, int bands);
+// LDS of a traceback work-group of `waves` waves (1..4, one wave per ticket)
+size_t tb_lds_bytes(int wpl, int sigma, int ckpt_every, int nb, int bands, int waves = 4);
 
 const void *fill_symbol(int wpl, int mode, bool raw, int sigma);
 int fill_block(int wpl, int sigma);   // threads per fill work-group
@@ -200,7 +201,7 @@ const void *tb_symbol(int wpl, int ckpt_every);
 
 hipError_t launch_prep(const PrepArgs &a, uint64_t xbytes_n, hipStream_t s);
 hipError_t launch_fill(int wpl, int mode, const FillArgs &a, uint32_t grid, hipStream_t s);
-hipError_t launch_tb(int wpl, const TbArgs &a, uint32_t grid, hipStream_t s);
+hipError_t launch_tb(int wpl, const TbArgs &a, uint32_t grid, int waves, hipStream_t s);
 hipError_t launch_emit(const EmitArgs &a, hipStream_t s);
 
 }  // namespace lcs

@@ -84,6 +84,7 @@ struct ClassDev {
     int fill_waves = 4;                // waves per fill work-group
     int nb = 1;                        // traceback tiles per band recomputed together
     int nbands = 1;                    // traceback bands recomputed together
+    int seal_nb = 1, seal_nbands = 1;  // the same for the seal pass (one-wave groups)
     uint32_t prio_half = 1;            // half the longest fill item's steps (wave priorities)
     // plain mode: one launch per pair and pass
     std::vector<uint32_t> pl_pair;     // pair of each launch
@@ -923,19 +924,32 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
                 tb_lds_bytes(C.wpl, sigma, cfg.ckpt, D.nb, D.nbands) > 160 * 1024)
                 return fail(LCS_ERR_ARG);
         }
+        // The seal pass walks each pair's strips one after another, one wave
+        // per pair: with so few waves LDS costs no residency, so its rounds
+        // recompute up to 64 tiles (one per lane) over up to 16 bands, in
+        // work-groups of one wave -- one batch of global reads per 16 bands
+        // instead of per two.
+        {
+            D.seal_nb = D.nb;
+            int bands = std::max(D.nbands, std::min(16, 64 / D.nb));
+            while (bands > D.nbands && tb_lds_bytes(C.wpl, sigma, cfg.ckpt, D.nb, bands, 1) > 160 * 1024)
+                --bands;
+            D.seal_nbands = bands;
+        }
         {
             const void *sym = tb_symbol(C.wpl, cfg.ckpt);
             const size_t lds = tb_lds_bytes(C.wpl, sigma, cfg.ckpt, D.nb, D.nbands);
+            const size_t slds = tb_lds_bytes(C.wpl, sigma, cfg.ckpt, D.seal_nb, D.seal_nbands, 1);
             D.sp_grid = resident_grid(ctx, sym, lds, (D.nsp + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
             D.fx_grid = resident_grid(ctx, sym, lds, (D.nfx + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
-            D.sl_grid = resident_grid(ctx, sym, lds, (D.nsl + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
+            D.sl_grid = resident_grid(ctx, sym, slds, D.nsl, cap, 64);
             for (uint32_t r = 0; r < C.n_rounds; ++r) {
                 const uint32_t nsp = C.rd_sp_off[r + 1] - C.rd_sp_off[r];
                 const uint32_t nfx = C.rd_fx_off[r + 1] - C.rd_fx_off[r];
                 const uint32_t nsl = C.rd_sl_off[r + 1] - C.rd_sl_off[r];
                 D.rd_sp_grid.push_back(resident_grid(ctx, sym, lds, (nsp + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0));
                 D.rd_fx_grid.push_back(resident_grid(ctx, sym, lds, (nfx + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0));
-                D.rd_sl_grid.push_back(resident_grid(ctx, sym, lds, (nsl + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0));
+                D.rd_sl_grid.push_back(resident_grid(ctx, sym, slds, nsl, cap, 64));
             }
         }
         if (bp->plain) {
@@ -1104,6 +1118,8 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
             ta.nticket = D.nfx;
             ta.queue = D.q_fix;
         } else {
+            ta.nb = D.seal_nb;
+            ta.nbands = D.seal_nbands;
             ta.tk_t = D.sl_t;
             ta.tk_s = nullptr;     // every seal runs from the pair's top strip down
             ta.tk_lo = nullptr;
@@ -1141,9 +1157,9 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
                 const ClassDev &D = b->cls[ci];
                 if (!D.ntb) continue;
                 if (!D.n_rounds) {
-                    HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbSpec), D.sp_grid, s));
-                    if (D.nfx) HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbFix), D.fx_grid, s));
-                    if (D.nsl) HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbSeal), D.sl_grid, s));
+                    HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbSpec), D.sp_grid, 4, s));
+                    if (D.nfx) HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbFix), D.fx_grid, 4, s));
+                    if (D.nsl) HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbSeal), D.sl_grid, 1, s));
                     continue;
                 }
                 // rounds: refill the round's items with their history in the
@@ -1172,20 +1188,22 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
                     ta.tk_s = D.rd_sp_s + D.rd_sp_off[r];
                     ta.nticket = D.rd_sp_off[r + 1] - D.rd_sp_off[r];
                     ta.queue = q + 1;
-                    if (ta.nticket) HIP_TRY(launch_tb(D.wpl, ta, D.rd_sp_grid[r], s));
+                    if (ta.nticket) HIP_TRY(launch_tb(D.wpl, ta, D.rd_sp_grid[r], 4, s));
                     ta.mode = kTbFix;
                     ta.tk_t = D.rd_fx_t + D.rd_fx_off[r];
                     ta.tk_s = D.rd_fx_s + D.rd_fx_off[r];
                     ta.nticket = D.rd_fx_off[r + 1] - D.rd_fx_off[r];
                     ta.queue = q + 2;
-                    if (ta.nticket) HIP_TRY(launch_tb(D.wpl, ta, D.rd_fx_grid[r], s));
+                    if (ta.nticket) HIP_TRY(launch_tb(D.wpl, ta, D.rd_fx_grid[r], 4, s));
                     ta.mode = kTbSeal;
                     ta.tk_t = D.rd_sl_t + D.rd_sl_off[r];
                     ta.tk_s = D.rd_sl_top + D.rd_sl_off[r];
                     ta.tk_lo = D.rd_sl_lo + D.rd_sl_off[r];
                     ta.nticket = D.rd_sl_off[r + 1] - D.rd_sl_off[r];
                     ta.queue = q + 3;
-                    if (ta.nticket) HIP_TRY(launch_tb(D.wpl, ta, D.rd_sl_grid[r], s));
+                    ta.nb = D.seal_nb;
+                    ta.nbands = D.seal_nbands;
+                    if (ta.nticket) HIP_TRY(launch_tb(D.wpl, ta, D.rd_sl_grid[r], 1, s));
                 }
             }
             HIP_TRY(launch_emit(ea, s));
@@ -1211,21 +1229,21 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
                     ta.tk_s += D.pl_sp[k];
                     ta.nticket = D.pl_nsp[k];
                     ta.queue = ctr + kQueues * k + 1;
-                    HIP_TRY(launch_tb(D.wpl, ta, (ta.nticket + 3) / 4, s));
+                    HIP_TRY(launch_tb(D.wpl, ta, (ta.nticket + 3) / 4, 4, s));
                     if (D.pl_nfx[k]) {
                         ta = tb_args(ci, kTbFix);
                         ta.tk_t += D.pl_fx[k];
                         ta.tk_s += D.pl_fx[k];
                         ta.nticket = D.pl_nfx[k];
                         ta.queue = ctr + kQueues * k + 2;
-                        HIP_TRY(launch_tb(D.wpl, ta, (ta.nticket + 3) / 4, s));
+                        HIP_TRY(launch_tb(D.wpl, ta, (ta.nticket + 3) / 4, 4, s));
                     }
                     if (D.pl_sl[k] != 0xffffffffu) {
                         ta = tb_args(ci, kTbSeal);
                         ta.tk_t += D.pl_sl[k];
                         ta.nticket = 1;
                         ta.queue = ctr + kQueues * k + 3;
-                        HIP_TRY(launch_tb(D.wpl, ta, 1, s));
+                        HIP_TRY(launch_tb(D.wpl, ta, 1, 1, s));
                     }
                     const uint32_t pr = D.pl_pair[k];
                     EmitArgs e1 = ea;

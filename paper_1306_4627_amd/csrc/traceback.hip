@@ -34,8 +34,8 @@ __host__ __device__ static inline size_t tb_wave_words(int wpl, int sigma, int K
            tb_even(slots * K / 4) + tb_even(slots * K / 64) + tb_even((size_t)bands);
 }
 
-size_t tb_lds_bytes(int wpl, int sigma, int K, int nb, int bands) {
-    return (size_t)(kTbBlock / 64) * tb_wave_words(wpl, sigma, K, nb, bands) * sizeof(uint64_t);
+size_t tb_lds_bytes(int wpl, int sigma, int K, int nb, int bands, int waves) {
+    return (size_t)waves * tb_wave_words(wpl, sigma, K, nb, bands) * sizeof(uint64_t);
 }
 
 // V of one band over the 2^LOGK steps of one tile, from the checkpoint V0
@@ -603,13 +603,15 @@ const void *tb_symbol(int wpl, int ckpt_every) {
 }
 #undef LCS_TB_SYM
 
-hipError_t launch_tb(int wpl, const TbArgs &a, uint32_t grid, hipStream_t s) {
+hipError_t launch_tb(int wpl, const TbArgs &a, uint32_t grid, int waves, hipStream_t s) {
     if (a.ckpt_every != 64 && a.ckpt_every != 128 && a.ckpt_every != 256) return hipErrorInvalidValue;
-    const size_t lds = tb_lds_bytes(wpl, a.sigma, a.ckpt_every, a.nb, a.nbands);
+    if (waves < 1 || waves > kTbBlock / 64) return hipErrorInvalidValue;
+    const size_t lds = tb_lds_bytes(wpl, a.sigma, a.ckpt_every, a.nb, a.nbands, waves);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
     const int logk = a.ckpt_every == 64 ? 6 : a.ckpt_every == 128 ? 7 : 8;
 #define LCS_TB_LAUNCH(W, L)                                                               \
     if (wpl == W && logk == L) {                                                          \
-        hipLaunchKernelGGL((k_traceback<W, L>), dim3(grid), dim3(kTbBlock), lds, s, a); \
+        hipLaunchKernelGGL((k_traceback<W, L>), dim3(grid), dim3(64 * waves), lds, s, a); \
         return hipGetLastError();                                                         \
     }
     LCS_TB_LAUNCH(1, 6) LCS_TB_LAUNCH(1, 7) LCS_TB_LAUNCH(1, 8)
