@@ -414,6 +414,8 @@ typedef struct {
     uint64_t plan_ns;          /* dispatcher time planning, uploading and launching batches */
     uint64_t collect_ns;       /* dispatcher time copying finished batches' results */
     uint64_t device_ns;        /* sum over batches of launch-to-completion time */
+    uint64_t tuned_batches;    /* batches launched with a tuning the context's
+                                  autotuner cache held for their shape */
 } lcs_server_stats;
 
 /* Start a server on the context (cfg may be NULL for the defaults). */

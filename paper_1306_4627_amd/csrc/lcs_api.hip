@@ -1788,7 +1788,13 @@ lcs_status batch_results(lcs_batch *b, std::vector<uint64_t> &lens,
 
 static uint32_t ilog2_u64(uint64_t v) { return v ? 63u - (uint32_t)__builtin_clzll(v) : 0u; }
 
+// The shape a tuning is cached under: what the batch computes (graph replay
+// and schedule records do not change the best tuning, so a batch tuned for
+// graph replay also serves the request server's eager batches), the
+// alphabet, and log2 buckets of the pair count, the longest X and Y and the
+// cells.
 static TuneKey tune_key(const lcs_pair *pairs, uint64_t count, int sigma, uint32_t flags) {
+    flags &= (uint32_t)(LCS_WANT_TRACEBACK | LCS_THRESHOLD);
     uint64_t mm = 0, mn = 0;
     double cells = 0;
     for (uint64_t k = 0; k < count; ++k) {

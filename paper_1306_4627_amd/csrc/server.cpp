@@ -291,7 +291,7 @@ void lcs_server::run() {
         // cost a second fill)
         hooks.avail = group.size() == 1 ? arena_bytes : 0;
         lcs_tuning tun{};
-        (void)lcs::tuning_cached(ctx, pairs.data(), pairs.size(), h.alpha_size, flags, &tun);
+        const bool tuned = lcs::tuning_cached(ctx, pairs.data(), pairs.size(), h.alpha_size, flags, &tun);
         lcs_batch *b = nullptr;
         lcs_status st = lcs::batch_create(ctx, pairs.data(), pairs.size(), &al, flags, &tun, &hooks, &b);
         if (!st) {
@@ -332,6 +332,7 @@ void lcs_server::run() {
             std::lock_guard<std::mutex> lk(mu);
             stats.plan_ns += t_launched - t_plan;
             ++stats.batches;
+            if (tuned) ++stats.tuned_batches;
             stats.max_inflight = std::max<uint64_t>(stats.max_inflight, flights.size() + 1);
         }
         Flight fl;

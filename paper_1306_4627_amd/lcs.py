@@ -78,7 +78,7 @@ class lcs_server_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "failed", "cancelled",
                                                 "queued", "batches", "max_inflight", "cells",
                                                 "arena_bytes", "arena_peak_bytes", "plan_ns",
-                                                "collect_ns", "device_ns")]
+                                                "collect_ns", "device_ns", "tuned_batches")]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

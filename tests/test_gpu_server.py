@@ -155,6 +155,24 @@ def test_server_errors_and_cancel(ctx, lcs):
         assert srv.poll(t1) == lcs.LCS_ERR_ARG      # collected tickets are gone
 
 
+def test_server_reuses_the_autotuners_tuning(ctx, lcs):
+    # a tuning found for graph replay is cached under the batch's shape
+    # without the graph flag, so the server's eager batch of the same shape
+    # (one request alone) launches with it
+    g = inputs.rng(7500)
+    x = inputs.random_seq(g, 30000, inputs.DNA)
+    y, _ = inputs.mutate(g, x, 0.1, inputs.DNA)
+    _say("server reuses a cached tuning")
+    lcs.autotune(ctx, [(x, y)], "dna", traceback=True, graph=True)
+    with lcs.Server(ctx, mem_budget_bytes=256 << 20, streams=1) as srv:
+        t = srv.submit(x, y, "dna", traceback=True)
+        assert srv.wait(t, 60_000_000) == 0
+        L, s, _ = srv.result(t)
+        st = srv.stats()
+    assert st["batches"] == 1 and st["tuned_batches"] == 1
+    assert s == oracle.lcs_traceback(x, y) and L == len(s)
+
+
 def _check_golden(k, e, L, s):
     assert L == e.length, f"request {k}: length {L} != {e.length}"
     if e.traceback:
