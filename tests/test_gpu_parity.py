@@ -429,6 +429,27 @@ def test_full_batch_related(ctx, lcs):
             assert not bad, f"replay {rep}: {len(bad)} strings differ, first {bad[:8]}"
 
 
+@pytest.mark.skipif(not gd.exists("full_batch_related.txt"), reason="golden not written")
+@pytest.mark.parametrize("waves", [1100, 2100, 3500])
+def test_full_batch_related_uneven_first_item_bands(ctx, lcs, waves):
+    # persistent grids of one, two and three first-item bands (waves per
+    # SIMD rounded down); where the work-groups land unevenly some SIMDs hold
+    # fewer waves, their bands' places are left to later waves, and chained
+    # items must still find their feeders
+    ps = inputs.batch_related()
+    pairs = [(p.x, p.y) for p in ps]
+    g = gd.batch_related()
+    _say(f"full related batch, {waves} persistent waves")
+    with lcs.Batch(ctx, pairs, "dna", traceback=True, words_per_lane=2, persistent_waves=waves) as b:
+        b.run()
+        L = b.lengths()
+        S = b.tracebacks()
+    bad = np.flatnonzero(L != g.lengths)
+    assert bad.size == 0, f"{bad.size} lengths differ, first {bad[:8]}"
+    bad = [k for k in range(len(S)) if gd.string_digest(S[k])[:32] != g.sha_prefix[k]]
+    assert not bad, f"{len(bad)} strings differ, first {bad[:8]}"
+
+
 @pytest.mark.skipif(not gd.exists("full_pair_long_related.txt"), reason="golden not written")
 def test_full_long_related_pair(ctx, lcs):
     p = inputs.pair_long_related()
