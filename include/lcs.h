@@ -116,9 +116,12 @@ typedef struct lcs_batch lcs_batch;
  *                    when the two need nearly the same number of column
  *                    steps.  Items linked this way form a run whose items all
  *                    wait on the one below; link_items caps a run's length
- *                    (default 1: a long pair always starts a new item; on the
- *                    4096-pair related batch 8-32 pack 6-8% fewer lane-steps
- *                    but run no faster).  Results do not depend on it.
+ *                    (default: 64 for traceback batches, whose fill the
+ *                    6-8% fewer lane-steps make about 10% faster on the
+ *                    4096-pair related batch; 1 -- a long pair always starts
+ *                    a new item -- for lengths-only and threshold batches,
+ *                    plain mode and traceback rounds).  Results do not
+ *                    depend on it.
  *  tb_round_kib    : traceback history held at once, in KiB (0 = automatic).
  *                    The fast form stores the checkpoints and carry bits of
  *                    every work item during the fill, about m*n/64 bits per

@@ -13,7 +13,8 @@ from paper_1306_4627_amd import inputs, lcs
 
 
 def _plans(m, n, sigma, kibs, **tuning):
-    full = lcs.plan_describe(m, n, sigma, traceback=True, **tuning)
+    # rounds keep chains unlinked: compare with the fast form packed the same way
+    full = lcs.plan_describe(m, n, sigma, traceback=True, **{"link_items": 1, **tuning})
     out = []
     for kib in kibs:
         try:
