@@ -70,10 +70,10 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def measured_traffic(workload: str, wpl: int, ckpt: int):
+def measured_traffic(workload: str, wpl: int, ckpt: int, lane_steps: int):
     """HBM bytes per fill launch from the committed rocprofv3 counter runs,
     or None when they were taken on a different kernel source, workload or
-    plan (words per lane, checkpoint interval)."""
+    plan (words per lane, checkpoint interval, lane-steps)."""
     import hashlib
     src = os.path.join(ROOT, "paper_1306_4627_amd", "csrc", "fill.hip")
     rec_file = os.path.join(ROOT, "profiles", "k_fill_batch_related_4096.md")
@@ -83,7 +83,8 @@ def measured_traffic(workload: str, wpl: int, ckpt: int):
             if line.startswith("traffic-record:"):
                 rec = json.loads(line.split(":", 1)[1])
                 if (rec["source_sha256_prefix"] == h and rec["workload"] == workload
-                        and rec.get("words_per_lane") == wpl and rec.get("ckpt_interval") == ckpt):
+                        and rec.get("words_per_lane") == wpl and rec.get("ckpt_interval") == ckpt
+                        and rec.get("lane_steps") == lane_steps):
                     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         pass
@@ -450,7 +451,7 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 1),
                      "unit": "TCUPS", "frac": round(achieved / peak, 4),
                      "traffic": measured_traffic(config["workload"], info["words_per_lane"],
-                                                 info["ckpt_interval"]),
+                                                 info["ckpt_interval"], info["lane_steps"]),
                      "kernel": "k_fill", "fill_ms": round(fill_avg, 4),
                      "compute_units": cus, "peak_clock_mhz": round(spec_mhz, 1),
                      "clock_mhz_measured": None if clock_mhz is None else round(clock_mhz, 1),
