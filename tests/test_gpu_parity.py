@@ -429,6 +429,34 @@ def test_full_batch_related(ctx, lcs):
             assert not bad, f"replay {rep}: {len(bad)} strings differ, first {bad[:8]}"
 
 
+@pytest.mark.parametrize("wpl,alname", [(1, "byte"), (2, "protein")])
+def test_unrelated_pairs_walked_by_the_seal(ctx, lcs, wpl, alname):
+    # unrelated pairs of several strips (walks from different entries rarely
+    # meet, so the seal re-walks most strips), beside a related pair and a
+    # short unrelated pair of one strip
+    g = inputs.rng(9100 + wpl)
+    pairs = []
+    shapes = (("dna", 20000, 20000), ("protein", 15000, 18000), ("byte", 12000, 9000), ("dna", 3000, 3500))
+    for al, m, n in shapes:
+        if alname == "protein" and al == "byte":
+            continue
+        x = inputs.random_seq(g, m, inputs.ALPHABETS[al])
+        y = inputs.random_seq(g, n, inputs.ALPHABETS[al])
+        pairs.append((x, y))
+    x = inputs.random_seq(g, 16000, inputs.DNA)
+    y, _ = inputs.mutate(g, x, 0.1, inputs.DNA)
+    pairs.append((x, y))
+    want = [oracle.lcs_traceback(x, y) for x, y in pairs]
+    _say(f"unrelated pairs walked by the seal, wpl {wpl}")
+    with lcs.Batch(ctx, pairs, alname, traceback=True, words_per_lane=wpl, strip_rows=4096) as b:
+        for rep in range(2):
+            b.run()
+            L = b.lengths()
+            S = b.tracebacks()
+            for k, s in enumerate(want):
+                assert S[k] == s and L[k] == len(s), (rep, k)
+
+
 @pytest.mark.skipif(not gd.exists("full_batch_related.txt"), reason="golden not written")
 @pytest.mark.parametrize("waves", [1100, 2100, 3500])
 def test_full_batch_related_uneven_first_item_bands(ctx, lcs, waves):
