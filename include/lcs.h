@@ -137,7 +137,24 @@ typedef struct lcs_batch lcs_batch;
  *                    memory left, else rounds sized to what is left after the
  *                    batch's other buffers.  The history of one work item is
  *                    8*(words_per_lane+1) bytes per column (the smallest
- *                    round); results do not depend on it. */
+ *                    round); results do not depend on it.
+ *  halves          : lengths-only batches (no traceback, no threshold, not
+ *                    plain): the length of a pair may be taken from two
+ *                    fills of half its columns each, run side by side --
+ *                    X against the first h = floor(n/2) symbols of Y, and X
+ *                    reversed against the rest of Y reversed -- as the
+ *                    largest sum, over the rows k, of the first half's
+ *                    c[k][h] and the second half's LCS of the last m - k
+ *                    symbols of X with the rest of Y (section I.C's table
+ *                    cut at column h, the middle-column split Hirschberg's
+ *                    method is built on).  A pair's column steps, the
+ *                    latency of its fill, halve; its cells stay the same.
+ *                    0 = automatic: split pairs of at least 4096 x 4096
+ *                    symbols when the batch at one word per lane, split,
+ *                    takes at most a quarter of the device's resident lanes
+ *                    (a batch too small to fill the device waits on its
+ *                    longest pair); 1 = never; 2 = every pair with n >= 2.
+ *                    Ignored for other batches; results do not depend on it. */
 typedef struct {
     int32_t words_per_lane;
     int32_t ckpt_interval;
@@ -148,6 +165,7 @@ typedef struct {
     int32_t tb_bands;
     int32_t link_items;
     int32_t tb_round_kib;
+    int32_t halves;
 } lcs_tuning;
 
 /* What a batch was planned into (filled by lcs_batch_info). */
@@ -163,7 +181,8 @@ typedef struct {
     int32_t classes;         /* kernel launches per run (fill) */
     int32_t flags;           /* LCS_WANT_TRACEBACK / LCS_USE_GRAPH as planned */
     int32_t tb_rounds;       /* traceback rounds (0: one pass, full history) */
-    int32_t reserved;
+    int32_t split_pairs;     /* pairs whose length comes from two half fills
+                                (lcs_tuning.halves) */
     uint64_t history_bytes;  /* device bytes of traceback history (checkpoints
                                 and carry bits, or the round buffer) */
 } lcs_batch_stats;

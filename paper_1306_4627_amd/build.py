@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblcs_hip.so")
-SOURCES = ["prep.hip", "fill.hip", "traceback.hip", "lcs_api.hip", "server.cpp", "plan.cpp"]
+SOURCES = ["prep.hip", "fill.hip", "halves.hip", "traceback.hip", "lcs_api.hip", "server.cpp",
+           "plan.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # gfx950 only; packed FP32 instructions are disabled for all device code.

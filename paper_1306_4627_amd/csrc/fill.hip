@@ -563,7 +563,15 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
 
         // ---- length: zero bits among the valid rows ----
         if (!a.out_len) continue;
-        const uint32_t zeros = lane_zeros<WPL>(vlo, vhi, pair, word0, m);
+        // a half of a split pair keeps its last column for the combine
+        const bool half = a.out_v && pair >= (int32_t)a.v_pair0;
+        if (half) {
+            uint64_t *dst = a.out_v + a.pair_vbase[pair - (int32_t)a.v_pair0];
+#pragma unroll
+            for (int q = 0; q < WPL; ++q)
+                if ((word0 + q) * 64u < m) dst[word0 + q] = ((uint64_t)vhi[q] << 32) | vlo[q];
+        }
+        const uint32_t zeros = half ? 0u : lane_zeros<WPL>(vlo, vhi, pair, word0, m);
         if (zeros) atomicAdd((unsigned long long *)(a.out_len + pair), (unsigned long long)zeros);
     }
 }

@@ -14,7 +14,23 @@ struct SegInfo {
     uint32_t len;     // region length in elements
     uint32_t pre;     // sentinel elements before column 0
     uint32_t n;       // columns of its pair (0 for an all-sentinel region)
-    uint32_t shift;   // log2 of the stream scale (words_per_lane * 512), or 0
+    uint32_t shift;   // log2 of the stream scale (words_per_lane * 512), or 0;
+                      // plus kSegReversed: column c holds Y[n - 1 - c]
+};
+
+constexpr uint32_t kSegReversed = 0x100;
+
+// A pair whose length comes from two fills of half its columns each: X
+// against Y[0, h), and X reversed against Y[h, n) reversed.  The reversed X
+// codes are written by the prep launch; the fill stores the last column of
+// both halves; k_halves combines them.
+struct HalfInfo {
+    uint64_t xsrc;    // the pair's X in the X arena (bytes)
+    uint64_t xdst;    // its reversed codes in the X-code arena
+    uint64_t vf;      // last column of the first half in the column buffer (words)
+    uint64_t vb;      // last column of the reversed second half
+    uint32_t pair;    // the pair whose length is written
+    uint32_t m;       // rows
 };
 
 // Symbol remap and Y-stream construction (all device pointers).
@@ -44,6 +60,9 @@ struct PrepArgs {
     const uint32_t *pair_n;
     const uint32_t *thr_t;
     uint32_t *thr_dec;
+    // split pairs (null when none): the reversed X codes of each
+    const HalfInfo *halves;
+    uint32_t nhalves;
 };
 
 // Fill: one class (fixed words per lane), persistent waves.
@@ -64,6 +83,11 @@ struct FillArgs {
     const uint32_t *ln_skew;
     const uint64_t *ln_ys;
     uint64_t *out_len;         // null: lengths not added (traceback rounds' refills)
+    // halves of split pairs: pairs from v_pair0 on store their last column
+    // at out_v + pair_vbase[pair - v_pair0] instead of adding a length
+    uint64_t *out_v;
+    const uint64_t *pair_vbase;
+    uint32_t v_pair0;
     uint64_t *ckpt;
     uint32_t *cbits;
     uint64_t *xfer;            // hand-over words, two per chunk per feeder (zeroed)
@@ -188,6 +212,14 @@ struct EmitArgs {
     uint32_t *error;            // set to 2 when a bitmap disagrees with the length
 };
 
+// Combine of split pairs: one work-group per pair.
+struct HalvesArgs {
+    const HalfInfo *halves;
+    uint32_t nhalves;
+    const uint64_t *v;         // last columns of the halves
+    uint64_t *out_len;
+};
+
 constexpr int kFillBlock = 256;   // at most four independent waves per work-group
 constexpr int kTbBlock = 256;
 
@@ -203,5 +235,6 @@ hipError_t launch_prep(const PrepArgs &a, uint64_t xbytes_n, hipStream_t s);
 hipError_t launch_fill(int wpl, int mode, const FillArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_tb(int wpl, const TbArgs &a, uint32_t grid, int waves, hipStream_t s);
 hipError_t launch_emit(const EmitArgs &a, hipStream_t s);
+hipError_t launch_halves(const HalvesArgs &a, hipStream_t s);
 
 }  // namespace lcs

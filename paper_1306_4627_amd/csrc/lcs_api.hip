@@ -107,6 +107,10 @@ struct ClassDev {
 // fix-up and seal passes
 constexpr int kQueues = 4;
 
+// Automatic middle-column split: pairs of at least this many symbols on
+// both sides.
+constexpr uint64_t kSplitMinSide = 4096;
+
 // Bump allocator over one device allocation.
 struct Carver {
     char *base = nullptr;
@@ -161,6 +165,19 @@ struct lcs_batch {
     uint32_t *error = nullptr;
     uint64_t *clk = nullptr;       // clock counters of the last fill launch
     uint64_t *junk = nullptr;      // fill: target of reads and stores a chunk does not need
+    // pairs split at the middle column (lengths only): the plan holds two
+    // halves per split pair, pairs npairs.. of the device pair tables; the
+    // reversed X codes of the second halves follow the X-code arena, 64
+    // bytes past its end; each half's last column goes to vcols
+    uint64_t nvirt = 0;
+    uint64_t xrev = 0;
+    std::vector<HalfInfo> halves_host;
+    HalfInfo *halves = nullptr;
+    uint64_t *pair_vbase = nullptr;
+    uint64_t *vcols = nullptr;
+    uint64_t vwords = 0;
+    uint32_t v_pair0 = 0;
+    std::vector<uint64_t> vbase_host;
     // threshold pass: per-pair target length (host copy and device) and
     // answer word (0 open, 1 reaches the target, 2 cannot; read back with the
     // lengths)
@@ -292,6 +309,7 @@ static lcs_status check_tuning(const lcs_tuning *t) {
         return LCS_ERR_ARG;
     if (t->persistent_waves < 0 || t->plain < 0 || t->plain > 1) return LCS_ERR_ARG;
     if (t->link_items < 0 || t->tb_round_kib < 0) return LCS_ERR_ARG;
+    if (t->halves < 0 || t->halves > 2) return LCS_ERR_ARG;
     if (t->strip_rows < 0 || t->tb_tiles < 0 || t->tb_tiles > 8 || t->tb_bands < 0 ||
         t->tb_bands > 16 || t->tb_tiles * t->tb_bands > 64)
         return LCS_ERR_ARG;
@@ -480,14 +498,17 @@ static size_t carve(lcs_batch *b, char *base) {
     b->lut = cv.take<uint8_t>(256);
     b->xbytes = cv.take<uint8_t>(b->xarena + 64);
     b->ybytes = cv.take<uint8_t>(b->yarena + 64);
-    b->pair_xoff = cv.take<uint64_t>(np + 1);
-    b->pair_yoff = cv.take<uint64_t>(np + 1);
+    const uint64_t npp = np + b->nvirt;   // pairs of the plan: the halves of split pairs too
+    b->pair_xoff = cv.take<uint64_t>(npp + 1);
+    b->pair_yoff = cv.take<uint64_t>(npp + 1);
     b->pair_out = cv.take<uint64_t>(np + 1);
     b->pair_diag = cv.take<uint64_t>(np + 1);
     b->em_pair = cv.take<uint32_t>(b->em_pair_host.size() + 1);
     b->em_w0 = cv.take<uint32_t>(b->em_w0_host.size() + 1);
-    b->pair_m = cv.take<uint32_t>(np + 1);
-    b->pair_n = cv.take<uint32_t>(np + 1);
+    b->pair_m = cv.take<uint32_t>(npp + 1);
+    b->pair_n = cv.take<uint32_t>(npp + 1);
+    b->halves = cv.take<HalfInfo>(b->halves_host.size() + 1);
+    b->pair_vbase = cv.take<uint64_t>(b->nvirt + 1);
     const bool thr = (b->flags & LCS_THRESHOLD) != 0;
     b->thr_t = thr ? cv.take<uint32_t>(np + 1) : nullptr;
     const size_t ns = p.segs.size();
@@ -562,8 +583,9 @@ static size_t carve(lcs_batch *b, char *base) {
     // ---- device only ----
     b->clk = cv.take<uint64_t>(4);
     b->junk = cv.take<uint64_t>(kJunkWords);
-    b->xcodes = cv.take<uint8_t>(b->xarena + 64);
+    b->xcodes = cv.take<uint8_t>(b->xarena + 64 + b->xrev + 64);
     b->ystream = cv.take<uint16_t>(p.ys_elems + 64);
+    b->vcols = cv.take<uint64_t>(b->vwords + 1);
     // zeroed before every pass, 64-bit: traceback bitmaps, then the carry
     // hand-over words of every class
     uint64_t nz64 = (b->flags & LCS_WANT_TRACEBACK) ? b->diag_words : 0;
@@ -721,6 +743,70 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     cfg.cus = ctx->num_cus;
     if (max_wpl(sigma) == 0) return LCS_ERR_UNSUPPORTED;
     if (cfg.wpl && !wpl_fits(sigma, cfg.wpl)) return LCS_ERR_UNSUPPORTED;
+    // Middle-column split (lengths only): pair k becomes two halves, pairs
+    // count + 2s (X against Y[0, h)) and count + 2s + 1 (X reversed against
+    // Y[h, n) reversed), h = n / 2; pair k itself is planned empty and its
+    // length written by the combine.
+    std::vector<uint32_t> hm(count + 1, 0), hn(count + 1, 0);
+    for (uint64_t k = 0; k < count; ++k) {
+        hm[k] = (uint32_t)pairs[k].m;
+        hn[k] = (uint32_t)pairs[k].n;
+    }
+    {
+        std::vector<uint64_t> split;
+        const int hv = tuning ? tuning->halves : 0;
+        if (!(flags & (LCS_WANT_TRACEBACK | LCS_THRESHOLD)) && !b->plain && hv != 1) {
+            if (hv == 2) {
+                for (uint64_t k = 0; k < count; ++k)
+                    if (pairs[k].m >= 1 && pairs[k].n >= 2) split.push_back(k);
+            } else {
+                uint64_t lanes = 0;   // at one word per lane, split pairs counted twice
+                for (uint64_t k = 0; k < count; ++k) {
+                    const bool c = pairs[k].m >= kSplitMinSide && pairs[k].n >= kSplitMinSide;
+                    lanes += (c ? 2 : 1) * ((pairs[k].m + 63) / 64);
+                    if (c) split.push_back(k);
+                }
+                if (lanes * 4 > (uint64_t)ctx->num_cus * 16 * 64) split.clear();
+            }
+        }
+        b->nvirt = 2 * split.size();
+        xoff.resize(count + b->nvirt + 1, 0);
+        yoff.resize(count + b->nvirt + 1, 0);
+        hm.resize(count + b->nvirt + 1, 0);
+        hn.resize(count + b->nvirt + 1, 0);
+        uint64_t roff = xa + 64, vw = 0;
+        std::vector<uint64_t> vbase;
+        for (size_t si = 0; si < split.size(); ++si) {
+            const uint64_t k = split[si], m = pairs[k].m, n = pairs[k].n, h = n / 2;
+            const uint64_t f = count + 2 * si, r = f + 1, W = (m + 63) / 64;
+            shapes[k].m = 0;
+            shapes.push_back(PairShape{m, h});
+            shapes.push_back(PairShape{m, n - h});
+            xoff[f] = xoff[k];
+            xoff[r] = roff;
+            yoff[f] = yoff[k];
+            yoff[r] = yoff[k] + h;
+            hm[f] = hm[r] = (uint32_t)m;
+            hn[f] = (uint32_t)h;
+            hn[r] = (uint32_t)(n - h);
+            HalfInfo hi{};
+            hi.xsrc = xoff[k];
+            hi.xdst = roff;
+            hi.vf = vw;
+            hi.vb = vw + W;
+            hi.pair = (uint32_t)k;
+            hi.m = (uint32_t)m;
+            b->halves_host.push_back(hi);
+            vbase.push_back(vw);
+            vbase.push_back(vw + W);
+            vw += 2 * W;
+            roff += (m + 63) / 64 * 64;
+        }
+        b->xrev = roff - (xa + 64);
+        b->vwords = vw;
+        b->v_pair0 = (uint32_t)count;
+        b->vbase_host = std::move(vbase);
+    }
     std::string why = build_plan(shapes, cfg, b->plan);
     if (!why.empty()) return plan_status(why);
     b->ckpt = cfg.ckpt;
@@ -787,11 +873,6 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         if (pairs[k].m) std::memcpy(image.data() + (bp->xbytes - (uint8_t *)dev0) + xoff[k], pairs[k].x, pairs[k].m);
         if (pairs[k].n) std::memcpy(image.data() + (bp->ybytes - (uint8_t *)dev0) + yoff[k], pairs[k].y, pairs[k].n);
     }
-    std::vector<uint32_t> hm(count + 1, 0), hn(count + 1, 0);
-    for (uint64_t k = 0; k < count; ++k) {
-        hm[k] = (uint32_t)pairs[k].m;
-        hn[k] = (uint32_t)pairs[k].n;
-    }
     const Plan &p = bp->plan;
     const size_t ns = p.segs.size();
     std::vector<SegInfo> seginfo(ns + 1);
@@ -806,8 +887,9 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         si.n = 0;
         si.yoff = 0;
         if (sg.pair != kNoPair) {
-            si.n = (uint32_t)pairs[sg.pair].n;
+            si.n = hn[sg.pair];
             si.yoff = yoff[sg.pair];
+            if (sg.pair >= count && ((sg.pair - count) & 1)) si.shift |= kSegReversed;
         }
     }
     hipStream_t st0 = bp->hooks.stream ? bp->hooks.stream : ctx->own_stream;
@@ -824,14 +906,16 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         if (e_ != hipSuccess) return fail(dev_err(e_)); \
     } while (0)
     UP(bp->lut, lut, 256);
-    UP(bp->pair_xoff, xoff.data(), count * 8);
-    UP(bp->pair_yoff, yoff.data(), count * 8);
+    UP(bp->pair_xoff, xoff.data(), (count + bp->nvirt) * 8);
+    UP(bp->pair_yoff, yoff.data(), (count + bp->nvirt) * 8);
     UP(bp->pair_out, bp->out_off_host.data(), count * 8);
     UP(bp->pair_diag, bp->diag_off_host.data(), count * 8);
     UP(bp->em_pair, bp->em_pair_host.data(), bp->em_pair_host.size() * 4);
     UP(bp->em_w0, bp->em_w0_host.data(), bp->em_w0_host.size() * 4);
-    UP(bp->pair_m, hm.data(), count * 4);
-    UP(bp->pair_n, hn.data(), count * 4);
+    UP(bp->pair_m, hm.data(), (count + bp->nvirt) * 4);
+    UP(bp->pair_n, hn.data(), (count + bp->nvirt) * 4);
+    UP(bp->halves, bp->halves_host.data(), bp->halves_host.size() * sizeof(HalfInfo));
+    UP(bp->pair_vbase, bp->vbase_host.data(), bp->vbase_host.size() * 8);
     UP(bp->seg, seginfo.data(), ns * sizeof(SegInfo));
     {
         // regions are whole 64-element blocks, back to back
@@ -1033,6 +1117,8 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         pa.thr_t = b->thr_t;
         pa.thr_dec = b->thr_dec;
     }
+    pa.halves = b->halves;
+    pa.nhalves = (uint32_t)b->halves_host.size();
     if (events) HIP_TRY(hipEventRecord(b->ev[0], s));
     HIP_TRY(launch_prep(pa, b->xarena + 64, s));
     if (events) HIP_TRY(hipEventRecord(b->ev[1], s));
@@ -1057,6 +1143,11 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         fa.ln_skew = D.ln_skew;
         fa.ln_ys = D.ln_ys;
         fa.out_len = b->out_len;
+        if (!b->halves_host.empty()) {
+            fa.out_v = b->vcols;
+            fa.pair_vbase = b->pair_vbase;
+            fa.v_pair0 = b->v_pair0;
+        }
         fa.ckpt = D.ckpt;
         fa.cbits = D.cbits;
         fa.xfer = D.xfer;
@@ -1159,6 +1250,14 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
             HIP_TRY(launch_fill(D.wpl, fwd_mode, fill_args(ci), D.fill_grid, s));
         }
         if (events) HIP_TRY(hipEventRecord(b->ev[2], s));
+        if (!b->halves_host.empty()) {
+            HalvesArgs ha{};
+            ha.halves = b->halves;
+            ha.nhalves = (uint32_t)b->halves_host.size();
+            ha.v = b->vcols;
+            ha.out_len = b->out_len;
+            HIP_TRY(launch_halves(ha, s));
+        }
         if (tb) {
             for (size_t ci = 0; ci < b->cls.size(); ++ci) {
                 const ClassDev &D = b->cls[ci];
@@ -1450,6 +1549,7 @@ extern "C" lcs_status lcs_batch_tracebacks(lcs_batch *b, uint8_t *out_arena, uin
 extern "C" lcs_status lcs_batch_info(const lcs_batch *b, lcs_batch_stats *out) {
     if (!b || !out) return LCS_ERR_ARG;
     stats_from_plan(b->plan, b->npairs, out);
+    out->split_pairs = (int32_t)b->halves_host.size();
     out->device_bytes = b->dev_bytes;
     out->history_bytes = b->history_bytes;
     out->flags = (int32_t)b->flags;

@@ -10,8 +10,8 @@ namespace lcs {
 // --------------------------------------------------------------------------
 
 // The work-groups of the one prep launch split into three ranges: the X
-// remap, the zeroing and the Y streams.  All three only depend on the
-// batch's inputs, so they run side by side.
+// remap (and the reversed X of split pairs), the zeroing and the Y streams.
+// All three only depend on the batch's inputs, so they run side by side.
 struct PrepSplit {
     uint32_t remap_end, zero_end, total;
 };
@@ -72,27 +72,49 @@ __device__ __forceinline__ void zero_words(const PrepArgs &a, uint32_t block, ui
         }
 }
 
+// Reversed codes of the X of every split pair (one byte per thread, the
+// rows past m of the last 64 set to code 0: the fill masks them out).  Each
+// copy starts 64-byte aligned in the X-code arena past the remapped range,
+// so the remap and these writes never meet.
+__device__ __forceinline__ void reverse_x(const uint8_t *lut, const PrepArgs &a, uint32_t block,
+                                          uint32_t blocks) {
+    const uint64_t tid = (uint64_t)block * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)blocks * blockDim.x;
+    for (uint32_t s = 0; s < a.nhalves; ++s) {
+        const HalfInfo h = a.halves[s];
+        const uint64_t padded = ((uint64_t)h.m + 63) / 64 * 64;
+        for (uint64_t r = tid; r < padded; r += stride)
+            a.xcodes[h.xdst + r] = r < h.m ? lut[a.xbytes[h.xsrc + h.m - 1 - r]] : (uint8_t)0;
+    }
+}
+
 // Eight stream values of a region from element kg on: codes of Y at columns
-// 0..n-1, the sentinel code everywhere else, each shifted into a byte offset
-// of its row of match masks; two per 32-bit word.
+// 0..n-1 (with `rev`, column c holds Y[n-1-c]), the sentinel code everywhere
+// else, each shifted into a byte offset of its row of match masks; two per
+// 32-bit word.
 __device__ __forceinline__ uint4 stream8(const uint8_t *lut, const uint8_t *y, uint64_t kg,
-                                         uint32_t pre, uint32_t n, uint32_t sh, uint32_t sent) {
+                                         uint32_t pre, uint32_t n, uint32_t sh, uint32_t sent,
+                                         bool rev) {
     uint32_t c[8];
     if (kg >= pre && kg + 8 <= (uint64_t)pre + n) {
         // eight bytes of Y from two aligned 8-byte reads (the Y arena is
-        // padded by 64 bytes)
-        const uintptr_t ad = (uintptr_t)(y + (kg - pre));
+        // padded by 64 bytes); reversed, the eight bytes ending at column
+        // n-1-(kg-pre), byte-swapped
+        const uint64_t c0 = kg - pre;
+        const uintptr_t ad = (uintptr_t)(y + (rev ? n - 8 - c0 : c0));
         const uint64_t *al = (const uint64_t *)(ad & ~(uintptr_t)7);
         const uint32_t s8 = (uint32_t)(ad & 7) * 8;
         const uint64_t lo = al[0], hi = al[1];
-        const uint64_t v = s8 ? (lo >> s8) | (hi << (64 - s8)) : lo;
+        uint64_t v = s8 ? (lo >> s8) | (hi << (64 - s8)) : lo;
+        if (rev) v = __builtin_bswap64(v);
 #pragma unroll
         for (int e = 0; e < 8; ++e) c[e] = (uint32_t)lut[(uint32_t)(v >> (8 * e)) & 0xffu] << sh;
     } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const uint64_t k = kg + e;
-            c[e] = (k >= pre && k - pre < n) ? ((uint32_t)lut[y[k - pre]] << sh) : sent;
+            const uint64_t col = k - pre;
+            c[e] = (k >= pre && col < n) ? ((uint32_t)lut[y[rev ? n - 1 - col : col]] << sh) : sent;
         }
     }
     uint4 v;
@@ -120,10 +142,12 @@ __device__ __forceinline__ void streams(const PrepArgs &a, const uint8_t *lut, u
         const uint64_t k0 = h * 32 - begin;   // element offset in the region
         if (k0 >= m1.x) continue;             // padding to the block
         const uint8_t *y = a.ybytes + yoff;
-        const uint32_t sent = (uint32_t)a.sentinel << m1.w;
+        const uint32_t sh = m1.w & (kSegReversed - 1);
+        const bool rev = (m1.w & kSegReversed) != 0;
+        const uint32_t sent = (uint32_t)a.sentinel << sh;
         uint4 v[4];
 #pragma unroll
-        for (int g = 0; g < 4; ++g) v[g] = stream8(lut, y, k0 + 8 * g, m1.y, m1.z, m1.w, sent);
+        for (int g = 0; g < 4; ++g) v[g] = stream8(lut, y, k0 + 8 * g, m1.y, m1.z, sh, sent, rev);
         uint4 *dst = (uint4 *)(a.ystream + h * 32);
 #pragma unroll
         for (int g = 0; g < 4; ++g)
@@ -138,6 +162,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a, uint64_t xbytes_n, Pre
     const uint32_t b = blockIdx.x;
     if (b < sp.remap_end) {
         remap_x(lut, a.xbytes, a.xcodes, xbytes_n, b, sp.remap_end);
+        if (a.nhalves) reverse_x(lut, a, b, sp.remap_end);
     } else if (b < sp.zero_end) {
         zero_words(a, b - sp.remap_end, sp.zero_end - sp.remap_end);
     } else {

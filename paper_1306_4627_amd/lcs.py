@@ -66,7 +66,7 @@ class lcs_tuning(ctypes.Structure):
                 ("persistent_waves", ctypes.c_int32), ("plain", ctypes.c_int32),
                 ("strip_rows", ctypes.c_int32), ("tb_tiles", ctypes.c_int32),
                 ("tb_bands", ctypes.c_int32), ("link_items", ctypes.c_int32),
-                ("tb_round_kib", ctypes.c_int32)]
+                ("tb_round_kib", ctypes.c_int32), ("halves", ctypes.c_int32)]
 
 
 class lcs_server_config(ctypes.Structure):
@@ -90,7 +90,7 @@ class lcs_batch_stats(ctypes.Structure):
                 ("lane_steps", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
                 ("words_per_lane", ctypes.c_int32), ("ckpt_interval", ctypes.c_int32),
                 ("classes", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("tb_rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tb_rounds", ctypes.c_int32), ("split_pairs", ctypes.c_int32),
                 ("history_bytes", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
@@ -259,10 +259,10 @@ def _alpha(a) -> Alphabet:
 
 
 def _tuning(words_per_lane=0, ckpt_interval=0, persistent_waves=0, plain=False, strip_rows=0,
-            tb_tiles=0, tb_bands=0, link_items=0, tb_round_kib=0):
+            tb_tiles=0, tb_bands=0, link_items=0, tb_round_kib=0, halves=0):
     return lcs_tuning(int(words_per_lane), int(ckpt_interval), int(persistent_waves), int(bool(plain)),
                       int(strip_rows), int(tb_tiles), int(tb_bands), int(link_items),
-                      int(tb_round_kib))
+                      int(tb_round_kib), int(halves))
 
 
 class _Pairs:
@@ -423,7 +423,8 @@ class Batch:
                  graph: bool = False, words_per_lane: int = 0, ckpt_interval: int = 0,
                  persistent_waves: int = 0, plain: bool = False, strip_rows: int = 0,
                  tb_tiles: int = 0, tb_bands: int = 0, threshold: Optional[float] = None,
-                 link_items: int = 0, fill_trace: bool = False, tb_round_kib: int = 0):
+                 link_items: int = 0, fill_trace: bool = False, tb_round_kib: int = 0,
+                 halves: int = 0):
         self.ctx = ctx
         self._pairs = _Pairs(pairs)
         self.count = self._pairs.count
@@ -436,7 +437,7 @@ class Batch:
         if fill_trace:
             flags |= LCS_FILL_TRACE
         t = _tuning(words_per_lane, ckpt_interval, persistent_waves, plain, strip_rows, tb_tiles,
-                    tb_bands, link_items, tb_round_kib)
+                    tb_bands, link_items, tb_round_kib, halves)
         h = ctypes.c_void_p()
         _check(_lib.lcs_batch_create(ctx.h, self._pairs.ptr(), self.count,
                                      ctypes.byref(self._alpha.c), flags, ctypes.byref(t),
