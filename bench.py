@@ -67,6 +67,10 @@ def make_workload(name: str):
         p = inputs.pair_long_related()
         return [p], "dna", True, {"workload": "pair_long_related", "m": int(p.x.size),
                                   "n": int(p.y.size), "alphabet": "DNA", "traceback": True}
+    if name == "pair_long_related_lengths":
+        p = inputs.pair_long_related()
+        return [p], "dna", False, {"workload": "pair_long_related_lengths", "m": int(p.x.size),
+                                   "n": int(p.y.size), "alphabet": "DNA", "traceback": False}
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -252,7 +256,7 @@ def batch_leg(lcs, ctx, pairs, alpha, traceback: bool, peak: float, steps: int, 
            "clock_mhz_measured": None if mhz is None else round(mhz, 1),
            "words_per_lane": info["words_per_lane"], "groups": info["groups"],
            "device_bytes": info["device_bytes"], "history_bytes": info["history_bytes"],
-           "tb_rounds": info["tb_rounds"], "tuning": tuning}
+           "tb_rounds": info["tb_rounds"], "split_pairs": info["split_pairs"], "tuning": tuning}
     if len(pairs) == 1:
         steps_per_item = info["lane_steps"] / (info["groups"] * 64)
         out["fill_ns_per_step"] = round(fill_ms * 1e6 / steps_per_item, 2)
@@ -465,7 +469,7 @@ def main() -> int:
                      "eager_pass_ms": round(float(np.mean(eager_ms)), 4)},
         "plan": {k: info[k] for k in ("groups", "lanes", "lane_steps", "words_per_lane",
                                       "ckpt_interval", "classes", "device_bytes", "history_bytes",
-                                      "tb_rounds")},
+                                      "tb_rounds", "split_pairs")},
         "tuning": {"chosen": tuning, "search_s": None if tune_s is None else round(tune_s, 2)},
     }
     if not args.no_plain and len(pairs) > 1:
@@ -526,6 +530,20 @@ def main() -> int:
                 leg["gpu_over_cpu_1_thread"] = round(leg["GCUPS"] / leg["cpu_oracle_1_thread"]["GCUPS"], 1)
             log(f"{name}: {leg}")
             wl[name] = leg
+        # the long pair's lengths-only pass: split at the middle column into
+        # two half fills run side by side (the default for a lone long pair),
+        # and whole
+        p2 = inputs.pair_long_related()
+        lw = {"config": {"workload": "pair_long_related", "m": int(p2.x.size), "n": int(p2.y.size),
+                         "alphabet": "DNA", "traceback": False}}
+        for key, hv in (("split", 0), ("whole", 1)):
+            lw[key] = batch_leg(lcs, ctx, [(p2.x, p2.y)], "dna", False, peak, 10,
+                                tuning={"words_per_lane": 1, "halves": hv})
+        lw["cells"] = float(p2.x.size) * float(p2.y.size)
+        lw["split_over_whole"] = round(lw["whole"]["pass_ms"] / lw["split"]["pass_ms"], 2)
+        del p2
+        log(f"pair_long_related lengths only: {lw}")
+        wl["pair_long_related_lengths"] = lw
         out["workloads"] = wl
         # traceback in rounds (bounded history) on the long pair and the batch
         log("rounds legs")

@@ -29,22 +29,32 @@ __device__ __forceinline__ uint64_t bit_window(const uint64_t *v, uint64_t s, ui
 
 // One work-group per split pair.  Each thread takes a run of consecutive
 // 64-row words and reduces it to (sum, best prefix) of f - g, the empty
-// prefix included; only rows where f and g differ change the sum, so it
-// visits those bits alone.  The runs are then joined in row order by a tree
-// of the (associative) join (s1, b1).(s2, b2) = (s1 + s2, max(b1, s1 + b2)).
+// prefix included, four rows at a time: a 256-entry table gives, for the four
+// rows' up bits (f and not g) and down bits (g and not f), their sum and best
+// prefix.  The runs are then joined in row order by a tree of the
+// (associative) join (s1, b1).(s2, b2) = (s1 + s2, max(b1, s1 + b2)).
 __global__ __launch_bounds__(kHalvesBlock) void k_halves(HalvesArgs a) {
-    __shared__ int64_t s_sum[kHalvesBlock], s_best[kHalvesBlock];
-    __shared__ unsigned long long s_g;
+    __shared__ int32_t s_sum[kHalvesBlock], s_best[kHalvesBlock];
+    __shared__ uint32_t s_g[kHalvesBlock];
+    __shared__ uint8_t s_tab[256];   // best | (sum + 4) << 4 of four rows
+    const uint32_t tid = threadIdx.x;
+    if (tid < 256) {
+        int32_t sm = 0, bs = 0;
+        for (int i = 0; i < 4; ++i) {
+            sm += (int32_t)((tid >> (4 + i)) & 1u) - (int32_t)((tid >> i) & 1u);
+            bs = sm > bs ? sm : bs;
+        }
+        s_tab[tid] = (uint8_t)(bs | ((sm + 4) << 4));
+    }
+    __syncthreads();
     const HalfInfo h = a.halves[blockIdx.x];
     const uint32_t m = h.m;
     const uint32_t W = (m + 63) / 64;
     const uint64_t *vf = a.v + h.vf;
     const uint64_t *vb = a.v + h.vb;
-    const uint32_t tid = threadIdx.x;
-    if (tid == 0) s_g = 0;
     const uint32_t per = (W + kHalvesBlock - 1) / kHalvesBlock;
     const uint32_t w0 = min(W, tid * per), w1 = min(W, w0 + per);
-    int64_t sum = 0, best = 0;
+    int32_t sum = 0, best = 0;
     uint32_t gsum = 0;
     for (uint32_t w = w0; w < w1; ++w) {
         const uint32_t row0 = w * 64;
@@ -56,31 +66,30 @@ __global__ __launch_bounds__(kHalvesBlock) void k_halves(HalvesArgs a) {
         const uint64_t win = bit_window(vb, (uint64_t)(m - row0 - cnt), cnt);
         const uint64_t g = ~(__builtin_bitreverse64(win) >> (64 - cnt)) & valid;
         gsum += (uint32_t)__builtin_popcountll(g);
-        const uint64_t up = f & ~g;
-        for (uint64_t d = f ^ g; d; d &= d - 1) {
-            const uint64_t low = d & (~d + 1);
-            if (up & low) {
-                ++sum;
-                best = sum > best ? sum : best;
-            } else {
-                --sum;
-            }
+        const uint64_t up = f & ~g, down = g & ~f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const uint32_t e = s_tab[(((uint32_t)(up >> (4 * q)) & 15u) << 4) |
+                                     ((uint32_t)(down >> (4 * q)) & 15u)];
+            const int32_t b4 = sum + (int32_t)(e & 15u);
+            best = b4 > best ? b4 : best;
+            sum += (int32_t)(e >> 4) - 4;
         }
     }
     s_sum[tid] = sum;
     s_best[tid] = best;
-    __syncthreads();
-    atomicAdd(&s_g, (unsigned long long)gsum);
+    s_g[tid] = gsum;
     for (uint32_t st = 1; st < kHalvesBlock; st *= 2) {
         __syncthreads();
         if ((tid & (2 * st - 1)) == 0) {
-            const int64_t b2 = s_sum[tid] + s_best[tid + st];
+            const int32_t b2 = s_sum[tid] + s_best[tid + st];
             s_best[tid] = b2 > s_best[tid] ? b2 : s_best[tid];
             s_sum[tid] += s_sum[tid + st];
+            s_g[tid] += s_g[tid + st];
         }
     }
     __syncthreads();
-    if (tid == 0) a.out_len[h.pair] = (uint64_t)s_g + (uint64_t)s_best[0];
+    if (tid == 0) a.out_len[h.pair] = (uint64_t)s_g[0] + (uint64_t)s_best[0];
 }
 
 hipError_t launch_halves(const HalvesArgs &a, hipStream_t s) {
