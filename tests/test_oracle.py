@@ -199,6 +199,27 @@ def test_invariants_random():
             assert d in (0, 1)
 
 
+def test_middle_column_split():
+    # The reading the lengths-only split rests on (section I.C's table cut at
+    # a column h): every path from (0, 0) to (m, n) crosses column h, so
+    # L(X, Y) = max over k of L(X[:k], Y[:h]) + L(X[k:], Y[h:]), and the
+    # second term is the length of the reversed suffixes.  Checked on the
+    # oracle for every h of small pairs, with brute force at the smallest.
+    g = np.random.default_rng(12)
+    for trial in range(40):
+        m, n = int(g.integers(0, 40)), int(g.integers(0, 40))
+        al = [b"AB", b"ACGT", b"ACDEFGHIKLMNPQRSTVWY"][trial % 3]
+        x, y = _rand_bytes(g, m, al), _rand_bytes(g, n, al)
+        L = oracle.lcs_length(x, y)
+        for h in range(n + 1):
+            best = max(oracle.lcs_length(x[:k], y[:h]) + oracle.lcs_length(x[k:][::-1], y[h:][::-1])
+                       for k in range(m + 1))
+            assert best == L, (x, y, h)
+    x, y = b"ACGTTGCA", b"TTGACCA"
+    assert max(oracle.brute_force_length(x[:k], y[:3]) + oracle.brute_force_length(x[k:], y[3:])
+               for k in range(len(x) + 1)) == oracle.brute_force_length(x, y)
+
+
 def test_chvatal_sankoff_range_dna():
     # statistical sanity only: L/n of random DNA pairs sits near 0.654
     p = inputs.pair_dna_4096(2048, 2048)
