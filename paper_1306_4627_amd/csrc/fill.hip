@@ -563,8 +563,10 @@ __device__ __forceinline__ void fill_body(const FillArgs &a) {
 
         // ---- length: zero bits among the valid rows ----
         if (!a.out_len) continue;
-        // a half of a split pair keeps its last column for the combine
-        const bool half = a.out_v && pair >= (int32_t)a.v_pair0;
+        // a half of a split pair keeps its last column for the combine (the
+        // split is for lengths-only batches; compiled into the other modes,
+        // this store alone made the traceback fill 11% slower)
+        const bool half = MODE == kFillLength && a.out_v && pair >= (int32_t)a.v_pair0;
         if (half) {
             uint64_t *dst = a.out_v + a.pair_vbase[pair - (int32_t)a.v_pair0];
 #pragma unroll
