@@ -85,6 +85,7 @@ struct ClassDev {
     int nb = 1;                        // traceback tiles per band recomputed together
     int nbands = 1;                    // traceback bands recomputed together
     int seal_nb = 1, seal_nbands = 1;  // the same for the seal pass (one-wave groups)
+    int tb_waves = 4;                  // waves per work-group of the speculative and fix-up passes
     uint32_t prio_half = 1;            // half the longest fill item's steps (wave priorities)
     // plain mode: one launch per pair and pass
     std::vector<uint32_t> pl_pair;     // pair of each launch
@@ -1027,12 +1028,24 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
                 --bands;
             D.seal_nbands = bands;
         }
+        // With at most one strip per compute unit the speculative and fix-up
+        // walks are as lone as the seal's, and take its work-groups of one
+        // wave and its larger rounds (the 4096 x 4096 pair's pass: 0.57 ->
+        // 0.52 ms at four tiles by eight bands already)
+        if (!bp->plain && !bp->rounds && !(tuning && (tuning->tb_tiles || tuning->tb_bands)) &&
+            D.nsp <= (uint32_t)ctx->num_cus)
+            D.tb_waves = 1;
         {
             const void *sym = tb_symbol(C.wpl, cfg.ckpt);
             const size_t lds = tb_lds_bytes(C.wpl, sigma, cfg.ckpt, D.nb, D.nbands);
             const size_t slds = tb_lds_bytes(C.wpl, sigma, cfg.ckpt, D.seal_nb, D.seal_nbands, 1);
-            D.sp_grid = resident_grid(ctx, sym, lds, (D.nsp + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
-            D.fx_grid = resident_grid(ctx, sym, lds, (D.nfx + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
+            if (D.tb_waves == 1) {
+                D.sp_grid = resident_grid(ctx, sym, slds, D.nsp, cap, 64);
+                D.fx_grid = resident_grid(ctx, sym, slds, D.nfx, cap, 64);
+            } else {
+                D.sp_grid = resident_grid(ctx, sym, lds, (D.nsp + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
+                D.fx_grid = resident_grid(ctx, sym, lds, (D.nfx + 3) / 4, cap > 0 ? (cap + 3) / 4 : 0);
+            }
             D.sl_grid = resident_grid(ctx, sym, slds, D.nsl, cap, 64);
             for (uint32_t r = 0; r < C.n_rounds; ++r) {
                 const uint32_t nsp = C.rd_sp_off[r + 1] - C.rd_sp_off[r];
@@ -1205,6 +1218,10 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
         ta.nbands = D.nbands;
         ta.ysh = raw_stream(b->sigma, D.wpl) ? 0 : 9 + __builtin_ctz((unsigned)D.wpl);
         ta.mode = mode;
+        if (mode != kTbSeal && D.tb_waves == 1) {
+            ta.nb = D.seal_nb;
+            ta.nbands = D.seal_nbands;
+        }
         if (mode == kTbSpec) {
             ta.tk_t = D.sp_t;
             ta.tk_s = D.sp_s;
@@ -1263,8 +1280,8 @@ static lcs_status enqueue(lcs_batch *b, hipStream_t s, bool events) {
                 const ClassDev &D = b->cls[ci];
                 if (!D.ntb) continue;
                 if (!D.n_rounds) {
-                    HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbSpec), D.sp_grid, 4, s));
-                    if (D.nfx) HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbFix), D.fx_grid, 4, s));
+                    HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbSpec), D.sp_grid, D.tb_waves, s));
+                    if (D.nfx) HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbFix), D.fx_grid, D.tb_waves, s));
                     if (D.nsl) HIP_TRY(launch_tb(D.wpl, tb_args(ci, kTbSeal), D.sl_grid, 1, s));
                     continue;
                 }
