@@ -1031,7 +1031,7 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
         // With at most one strip per compute unit the speculative and fix-up
         // walks are as lone as the seal's, and take its work-groups of one
         // wave and its larger rounds (the 4096 x 4096 pair's pass: 0.57 ->
-        // 0.52 ms at four tiles by eight bands already)
+        // 0.53 ms)
         if (!bp->plain && !bp->rounds && !(tuning && (tuning->tb_tiles || tuning->tb_bands)) &&
             D.nsp <= (uint32_t)ctx->num_cus)
             D.tb_waves = 1;
