@@ -11,6 +11,8 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
+#include <utility>
 #include <new>
 #include <string>
 #include <tuple>
@@ -285,9 +287,51 @@ static lcs_status make_lut(const lcs_alphabet *a, uint8_t lut[256], bool valid[2
 }
 
 static bool all_in(const uint8_t *s, uint64_t len, const bool valid[256]) {
-    for (uint64_t k = 0; k < len; ++k)
-        if (!valid[s[k]]) return false;
+    // branch-free over blocks of 4 KiB, one test per block
+    for (uint64_t k = 0; k < len;) {
+        const uint64_t e = std::min<uint64_t>(len, k + 4096);
+        unsigned ok = 1;
+        for (; k < e; ++k) ok &= (unsigned)valid[s[k]];
+        if (!ok) return false;
+    }
     return true;
+}
+
+// Host threads for work over `bytes` of input: one per 4 MiB, at most 16.
+static int host_threads(uint64_t bytes) {
+    const uint64_t hc = std::max(1u, std::thread::hardware_concurrency());
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(std::min<uint64_t>(bytes >> 22, hc), 16));
+}
+
+// fn(t) for t in [0, T): the calling thread takes t = 0, T - 1 more threads
+// the rest (the calling thread runs the tasks of any thread that cannot be
+// started).
+template <class F>
+static void run_threads(int T, F fn) {
+    std::vector<std::thread> th;
+    int t = 1;
+    try {
+        for (; t < T; ++t) th.emplace_back(fn, t);
+    } catch (...) {
+        for (; t < T; ++t) fn(t);
+    }
+    fn(0);
+    for (std::thread &x : th) x.join();
+}
+
+// Pair ranges of T tasks with about the same bytes of X and Y each.
+static std::vector<uint64_t> pair_ranges(const lcs_pair *pairs, uint64_t count, int T) {
+    uint64_t total = 0;
+    for (uint64_t k = 0; k < count; ++k) total += pairs[k].m + pairs[k].n;
+    std::vector<uint64_t> lo((size_t)T + 1, count);
+    lo[0] = 0;
+    uint64_t acc = 0;
+    int t = 1;
+    for (uint64_t k = 0; k < count && t < T; ++k) {
+        acc += pairs[k].m + pairs[k].n;
+        while (t < T && acc * (uint64_t)T >= total * (uint64_t)t) lo[(size_t)t++] = k + 1;
+    }
+    return lo;
 }
 
 static lcs_status check_pairs(const lcs_pair *pairs, uint64_t count) {
@@ -689,9 +733,22 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     int sigma = 0;
     st = make_lut(alphabet, lut, valid, &sigma);
     if (st) return st;
-    for (uint64_t k = 0; k < count; ++k) {
-        if (!all_in(pairs[k].x, pairs[k].m, valid)) return LCS_ERR_SYMBOL;
-        if (!all_in(pairs[k].y, pairs[k].n, valid)) return LCS_ERR_SYMBOL;
+    {
+        // every byte against the alphabet, before anything is allocated
+        uint64_t in_bytes = 0;
+        for (uint64_t k = 0; k < count; ++k) in_bytes += pairs[k].m + pairs[k].n;
+        const int T = host_threads(in_bytes);
+        const std::vector<uint64_t> rg = pair_ranges(pairs, count, T);
+        std::vector<uint8_t> bad((size_t)T, 0);
+        run_threads(T, [&](int t) {
+            for (uint64_t k = rg[(size_t)t]; k < rg[(size_t)t + 1]; ++k)
+                if (!all_in(pairs[k].x, pairs[k].m, valid) || !all_in(pairs[k].y, pairs[k].n, valid)) {
+                    bad[(size_t)t] = 1;
+                    return;
+                }
+        });
+        for (uint8_t v : bad)
+            if (v) return LCS_ERR_SYMBOL;
     }
     std::unique_ptr<lcs_batch> b(new (std::nothrow) lcs_batch());
     if (!b) return LCS_ERR_NOMEM;
@@ -868,11 +925,29 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     };
     // the host image of [0, upload_bytes): every host-written region at its
     // device offset, sent with one copy
-    std::vector<uint8_t> image(bp->upload_bytes, 0);
+    // (X and Y are copied by host threads; every other byte of the image is
+    // zeroed once, and each pair's X padding with its copy)
     char *const dev0 = (char *)bp->dev;
-    for (uint64_t k = 0; k < count; ++k) {
-        if (pairs[k].m) std::memcpy(image.data() + (bp->xbytes - (uint8_t *)dev0) + xoff[k], pairs[k].x, pairs[k].m);
-        if (pairs[k].n) std::memcpy(image.data() + (bp->ybytes - (uint8_t *)dev0) + yoff[k], pairs[k].y, pairs[k].n);
+    const size_t img_bytes = bp->upload_bytes;
+    std::unique_ptr<uint8_t[]> image_buf(new (std::nothrow) uint8_t[img_bytes ? img_bytes : 1]);
+    if (!image_buf) return fail(LCS_ERR_NOMEM);
+    uint8_t *const img = image_buf.get();
+    {
+        const size_t xo = (size_t)((char *)bp->xbytes - dev0), yo = (size_t)((char *)bp->ybytes - dev0);
+        if (!(xo + xa <= yo && yo + ya <= img_bytes)) return fail(LCS_ERR_DEVICE);
+        std::memset(img, 0, xo);
+        std::memset(img + xo + xa, 0, yo - (xo + xa));
+        std::memset(img + yo + ya, 0, img_bytes - (yo + ya));
+        const int T = host_threads(xa + ya);
+        const std::vector<uint64_t> rg = pair_ranges(pairs, count, T);
+        run_threads(T, [&](int t) {
+            for (uint64_t k = rg[(size_t)t]; k < rg[(size_t)t + 1]; ++k) {
+                const uint64_t m = pairs[k].m, pad = (m + 63) / 64 * 64;
+                if (m) std::memcpy(img + xo + xoff[k], pairs[k].x, m);
+                if (pad > m) std::memset(img + xo + xoff[k] + m, 0, pad - m);
+                if (pairs[k].n) std::memcpy(img + yo + yoff[k], pairs[k].y, pairs[k].n);
+            }
+        });
     }
     const Plan &p = bp->plan;
     const size_t ns = p.segs.size();
@@ -897,8 +972,8 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
         if (!bytes) return hipSuccess;
         const size_t off = (size_t)((char *)dst - dev0);
-        if (off + bytes > image.size()) return hipErrorInvalidValue;
-        std::memcpy(image.data() + off, src, bytes);
+        if (off + bytes > img_bytes) return hipErrorInvalidValue;
+        std::memcpy(img + off, src, bytes);
         return hipSuccess;
     };
 #define UP(dst, src, bytes)                          \
@@ -1085,7 +1160,7 @@ static lcs_status build_batch(lcs_ctx *ctx, const lcs_pair *pairs, uint64_t coun
     }
 #undef UP
     if (bp->upload_bytes &&
-        hipMemcpyAsync(bp->dev, image.data(), bp->upload_bytes, hipMemcpyHostToDevice, st0) != hipSuccess)
+        hipMemcpyAsync(bp->dev, img, bp->upload_bytes, hipMemcpyHostToDevice, st0) != hipSuccess)
         return fail(LCS_ERR_DEVICE);
     if (hipStreamSynchronize(st0) != hipSuccess) return fail(LCS_ERR_DEVICE);
     bp->no_events = no_events;
@@ -1443,7 +1518,29 @@ static lcs_status finish(lcs_batch *b) {
 // the lengths and the error word, and with `strings` also the LCS bytes (the
 // three regions are adjacent on the device).  LCS_ERR_DEVICE if a kernel set
 // the error word.
-static lcs_status readback(lcs_batch *b, bool strings, std::vector<uint8_t> &host) {
+// Byte vector whose growth leaves the new bytes uninitialized: a read-back
+// image is overwritten by the copy at once.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() = default;
+    template <class U>
+    NoInitAlloc(const NoInitAlloc<U> &) {}
+    template <class U>
+    void construct(U *p) noexcept {
+        ::new ((void *)p) U;
+    }
+    template <class U, class... A>
+    void construct(U *p, A &&...a) {
+        ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+using HostBytes = std::vector<uint8_t, NoInitAlloc<uint8_t>>;
+
+static lcs_status readback(lcs_batch *b, bool strings, HostBytes &host) {
     if (!b->ran) return LCS_ERR_ARG;
     lcs_ctx *ctx = b->ctx;
     if (hipSetDevice(ctx->device) != hipSuccess) return LCS_ERR_DEVICE;
@@ -1465,7 +1562,7 @@ static lcs_status readback(lcs_batch *b, bool strings, std::vector<uint8_t> &hos
 
 // Threshold pass: answers and lengths from a read-back image (a pair
 // answered before its last column has no length).
-static lcs_status threshold_results(const lcs_batch *b, const std::vector<uint8_t> &host,
+static lcs_status threshold_results(const lcs_batch *b, const HostBytes &host,
                                     uint8_t *out_pass, uint64_t *out_len) {
     const uint64_t *L = (const uint64_t *)host.data();
     const uint32_t *dec = (const uint32_t *)(host.data() + ((char *)b->thr_dec - (char *)b->out_len));
@@ -1489,7 +1586,7 @@ static lcs_status threshold_results(const lcs_batch *b, const std::vector<uint8_
 
 extern "C" lcs_status lcs_batch_lengths(lcs_batch *b, uint64_t *out_lens) {
     if (!b || (b->npairs && !out_lens)) return LCS_ERR_ARG;
-    std::vector<uint8_t> host;
+    HostBytes host;
     lcs_status st = readback(b, false, host);
     if (st) return st;
     if (b->flags & LCS_THRESHOLD) return threshold_results(b, host, nullptr, out_lens);
@@ -1534,7 +1631,7 @@ extern "C" lcs_status lcs_batch_set_threshold(lcs_batch *b, double min_percent) 
 extern "C" lcs_status lcs_batch_decisions(lcs_batch *b, uint8_t *out_pass, uint64_t *out_len) {
     if (!b || !(b->flags & LCS_THRESHOLD)) return LCS_ERR_ARG;
     if (b->npairs && !out_pass) return LCS_ERR_ARG;
-    std::vector<uint8_t> host;
+    HostBytes host;
     lcs_status st = readback(b, false, host);
     if (st) return st;
     return threshold_results(b, host, out_pass, out_len);
@@ -1547,7 +1644,7 @@ extern "C" lcs_status lcs_batch_tracebacks(lcs_batch *b, uint8_t *out_arena, uin
     if (b->npairs && (!out_offsets || !out_lens)) return LCS_ERR_ARG;
     if (arena_cap < b->out_off_host[b->npairs]) return LCS_ERR_BUFFER;
     if (b->out_off_host[b->npairs] && !out_arena) return LCS_ERR_ARG;
-    std::vector<uint8_t> host;
+    HostBytes host;
     lcs_status st = readback(b, true, host);
     if (st) return st;
     const uint64_t *L = (const uint64_t *)host.data();

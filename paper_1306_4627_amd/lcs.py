@@ -272,10 +272,12 @@ class _Pairs:
         self.bufs = []
         self.arr = (lcs_pair * max(1, len(pairs)))()
         self.count = len(pairs)
+        self.cap = 0   # sum of min(m, n): the output capacity of the strings
         for k, (x, y) in enumerate(pairs):
             xa, ya = _as_u8(x), _as_u8(y)
             self.bufs += [xa, ya]
             self.arr[k] = lcs_pair(_u8p(xa), xa.size, _u8p(ya), ya.size)
+            self.cap += min(xa.size, ya.size)
 
     def ptr(self):
         return self.arr if self.count else ctypes.POINTER(lcs_pair)()
@@ -357,8 +359,8 @@ def lcs_length_batch(ctx: Context, pairs, alphabet="dna") -> np.ndarray:
 def lcs_traceback_batch(ctx: Context, pairs, alphabet="dna") -> List[bytes]:
     pp = _Pairs(pairs)
     al = _alpha(alphabet)
-    cap = sum(min(len(_as_u8(x)), len(_as_u8(y))) for x, y in pairs)
-    arena = np.zeros(max(1, cap), dtype=np.uint8)
+    cap = pp.cap
+    arena = np.empty(max(1, cap), dtype=np.uint8)   # written where read back
     offs = np.zeros(max(1, pp.count), dtype=np.uint64)
     lens = np.zeros(max(1, pp.count), dtype=np.uint64)
     P64 = ctypes.POINTER(ctypes.c_uint64)
@@ -373,8 +375,8 @@ def lcs_traceback_batch_noalloc(ctx: Context, pairs, alphabet="dna") -> List[byt
     fixed device scratch array (no device allocation)."""
     pp = _Pairs(pairs)
     al = _alpha(alphabet)
-    cap = sum(min(len(_as_u8(x)), len(_as_u8(y))) for x, y in pairs)
-    arena = np.zeros(max(1, cap), dtype=np.uint8)
+    cap = pp.cap
+    arena = np.empty(max(1, cap), dtype=np.uint8)   # written where read back
     offs = np.zeros(max(1, pp.count), dtype=np.uint64)
     lens = np.zeros(max(1, pp.count), dtype=np.uint64)
     P64 = ctypes.POINTER(ctypes.c_uint64)
@@ -430,7 +432,7 @@ class Batch:
         self.count = self._pairs.count
         self._alpha = _alpha(alphabet)
         self.traceback = traceback
-        self.cap = sum(min(len(_as_u8(x)), len(_as_u8(y))) for x, y in pairs)
+        self.cap = self._pairs.cap
         flags = (LCS_WANT_TRACEBACK if traceback else 0) | (LCS_USE_GRAPH if graph else 0)
         if threshold is not None:
             flags |= LCS_THRESHOLD
@@ -470,7 +472,7 @@ class Batch:
         return out[:self.count]
 
     def tracebacks(self) -> List[bytes]:
-        arena = np.zeros(max(1, self.cap), dtype=np.uint8)
+        arena = np.empty(max(1, self.cap), dtype=np.uint8)   # written where read back
         offs = np.zeros(max(1, self.count), dtype=np.uint64)
         lens = np.zeros(max(1, self.count), dtype=np.uint64)
         P64 = ctypes.POINTER(ctypes.c_uint64)
