@@ -343,6 +343,27 @@ def test_error_paths_leave_outputs_untouched(ctx, lcs):
     small.close()
 
 
+@pytest.mark.parametrize("where", ["first", "middle", "last"])
+def test_symbol_errors_in_large_batches(ctx, lcs, where):
+    # a batch large enough that its bytes are validated by several host
+    # threads (about 96 MB): one foreign byte in the first, a middle or the
+    # last pair is found, and nothing runs
+    g = inputs.rng(7400)
+    base = _rand(g, 1 << 20, inputs.DNA)
+    pairs = [(base, base) for _ in range(48)]
+    k = {"first": 0, "middle": 23, "last": 47}[where]
+    bad = base.copy()
+    bad[len(bad) // 2 + k] = ord("N")
+    pairs[k] = (base, bad) if k % 2 else (bad, base)
+    _say(f"symbol error in a large batch ({where})")
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.Batch(ctx, pairs, "dna")
+    assert e.value.status == lcs.LCS_ERR_SYMBOL
+    with pytest.raises(lcs.LcsError) as e:
+        lcs.lcs_length_batch(ctx, pairs, "dna")
+    assert e.value.status == lcs.LCS_ERR_SYMBOL
+
+
 @pytest.mark.parametrize("sigma", [20, 40])
 def test_lengths_with_next_item_prefetch(ctx, lcs, sigma):
     # alphabets whose match masks leave two waves or fewer per SIMD at two
