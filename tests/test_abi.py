@@ -226,3 +226,30 @@ def test_traceback_strip_tables(strip_rows):
     for w in (1, 2, 4, 8):
         assert lcs.plan_selfcheck(m, n, 4, traceback=True, words_per_lane=w,
                                   strip_rows=strip_rows) == 0
+
+
+def _header_struct_fields(name):
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r"\s*;", text).group(1)
+    return [re.findall(r"(\w+)\s*;", line)[0] for line in body.splitlines() if ";" in line]
+
+
+@pytest.mark.parametrize("name", ["lcs_tuning", "lcs_batch_stats", "lcs_pair"])
+def test_binding_structs_mirror_the_header(name):
+    # the ctypes mirrors list the header's fields in the header's order
+    ours = [f for f, _ in getattr(lcs, name)._fields_]
+    assert ours == _header_struct_fields(name)
+
+
+def test_halves_setting_is_checked():
+    L = lcs.lib()
+    m = np.array([5000, 9000], dtype=np.uint64)
+    P64 = ctypes.POINTER(ctypes.c_uint64)
+    mp = m.ctypes.data_as(P64)
+    s = lcs.lcs_batch_stats()
+    for hv, want in ((0, lcs.LCS_OK), (1, lcs.LCS_OK), (2, lcs.LCS_OK), (3, lcs.LCS_ERR_ARG),
+                     (-1, lcs.LCS_ERR_ARG)):
+        t = lcs.lcs_tuning()
+        t.halves = hv
+        assert L.lcs_plan_describe(mp, mp, 2, 4, 0, ctypes.byref(t), ctypes.byref(s)) == want
