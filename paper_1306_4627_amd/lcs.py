@@ -270,17 +270,24 @@ class _Pairs:
 
     def __init__(self, pairs: Sequence[Tuple[object, object]]):
         self.bufs = []
-        self.arr = (lcs_pair * max(1, len(pairs)))()
         self.count = len(pairs)
-        self.cap = 0   # sum of min(m, n): the output capacity of the strings
-        for k, (x, y) in enumerate(pairs):
+        # the lcs_pair array as one record array: {x, m, y, n}, 8 bytes each
+        words = []
+        for x, y in pairs:
             xa, ya = _as_u8(x), _as_u8(y)
             self.bufs += [xa, ya]
-            self.arr[k] = lcs_pair(_u8p(xa), xa.size, _u8p(ya), ya.size)
-            self.cap += min(xa.size, ya.size)
+            words += [xa.__array_interface__["data"][0] if xa.size else 0, xa.size,
+                      ya.__array_interface__["data"][0] if ya.size else 0, ya.size]
+        self.rec = np.array(words if words else [0, 0, 0, 0], dtype=np.uint64)
+        m = self.rec[1::4]
+        n = self.rec[3::4]
+        # sum of min(m, n): the output capacity of the strings
+        self.cap = int(np.minimum(m, n).sum()) if self.count else 0
 
     def ptr(self):
-        return self.arr if self.count else ctypes.POINTER(lcs_pair)()
+        if not self.count:
+            return ctypes.POINTER(lcs_pair)()
+        return ctypes.cast(self.rec.ctypes.data, ctypes.POINTER(lcs_pair))
 
 
 class Context:
