@@ -1654,9 +1654,16 @@ extern "C" lcs_status lcs_batch_tracebacks(lcs_batch *b, uint8_t *out_arena, uin
         if (L[k] > std::min(b->m[k], b->n[k])) return LCS_ERR_DEVICE;
         out_offsets[k] = o;
         out_lens[k] = L[k];
-        if (L[k]) std::memcpy(out_arena + o, raw + b->out_off_host[k], L[k]);
         o += L[k];
     }
+    // the strings into the caller's arena, pairs split over host threads
+    const int T = host_threads(o);
+    const uint64_t np = b->npairs;
+    run_threads(T, [&](int t) {
+        const uint64_t k0 = np * (uint64_t)t / (uint64_t)T, k1 = np * (uint64_t)(t + 1) / (uint64_t)T;
+        for (uint64_t k = k0; k < k1; ++k)
+            if (L[k]) std::memcpy(out_arena + out_offsets[k], raw + b->out_off_host[k], L[k]);
+    });
     return LCS_OK;
 }
 
